@@ -1,0 +1,241 @@
+/*
+ * pw_advect.h -- C ABI of the MI355X (gfx950) Piacsek-Williams advection library.
+ *
+ * The library computes the PW momentum-advection source terms su, sv, sw from
+ * the wind fields u, v, w (N. Brown, "Accelerating advection for atmospheric
+ * modelling on Xilinx and Intel FPGAs", Sec. II-A, Listing 1):
+ *
+ *   su  Listing 1: x flux term (tcx), y flux term (tcy), vertical term with
+ *       tzc1 (lower face) and tzc2 (upper face), for k = 2..nz; at k = nz the
+ *       upper vertical flux is dropped.
+ *   sv  the x<->y mirror of su on the same staggered (Arakawa C) grid
+ *       (v on y faces): y term first with tcy, then x term with tcx, then the
+ *       vertical term with tzc1/tzc2; k = 2..nz, truncated at k = nz likewise.
+ *   sw  the same staggering rule for w on z faces: x and y flux terms with u,
+ *       v summed across the two levels k, k+1, and a vertical term in w with
+ *       tzd1 (lower) and tzd2 (upper); k = 2..nz-1.
+ *   Every output is written as 0 at k = 1, and sw at k = nz.
+ *
+ * The paper prints only su; sv and sw follow the staggering that Listing 1's
+ * indices imply and the 21 operations per field that Sec. III counts.
+ *
+ * Layout (Listing 1, Fortran u(k, j, i)): element (k, j, i) with k in 1..nz,
+ * j in 0..ny+1, i in 0..nx+1 sits at element offset
+ *     (k - 1) + j * sy + i * sx
+ * from the array base: k (vertical) is fastest, a one-point halo surrounds the
+ * interior in x and y, there is no vertical halo.  Default strides are
+ * sy = nz and sx = (ny + 2) * sy.  All six arrays of one domain share the
+ * shape and strides.  Every interior column (i in 1..nx, j in 1..ny) of every
+ * output is fully written (all k); halo columns of the outputs are never
+ * touched.  The caller fills the input halos (including the corner columns,
+ * which sv and su read) before the call.
+ *
+ * Storage precision: PW_F64 computes in FP64.  PW_F32, PW_BF16 and PW_F16
+ * store all six arrays in that type and compute in FP32 with each product
+ * difference a*b - c*d evaluated in compensated form (Kahan's fused
+ * multiply-add algorithm); the vertical coefficients stay FP64 in memory and
+ * are rounded to FP32 once per thread.  For the 16-bit types each field has a
+ * power-of-two scale: stored = value * scale.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named "device" are HIP device (or managed) pointers owned by
+ *    the caller; the library never frees them.  Pointers named "host" are
+ *    read before the call returns.
+ *  - Functions return a pw_status (PW_OK = 0, errors negative) and never
+ *    throw.  Argument errors are detected on the host before anything is
+ *    launched.  A failed HIP call returns PW_ERR_HIP and its hipError_t is
+ *    kept for pw_last_hip_error() (per host thread).  Faults inside a kernel
+ *    surface at the caller's next synchronisation, as with any HIP launch.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *    Compute entry points are asynchronous on that stream, never synchronise
+ *    and never allocate, so they may be recorded into a HIP graph.
+ */
+#ifndef PW_ADVECT_H
+#define PW_ADVECT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+    PW_OK = 0,
+    PW_ERR_INVALID_ARG = -1,   /* null pointer, bad size or stride, bad tuning value */
+    PW_ERR_UNSUPPORTED = -2,   /* unknown dtype or variant, or no GPU device */
+    PW_ERR_ALIAS = -3,         /* an output overlaps an input or another output */
+    PW_ERR_ALIGNMENT = -4,     /* a pointer is not aligned to its element size */
+    PW_ERR_OUT_OF_MEMORY = -5, /* plan tables could not be allocated */
+    PW_ERR_HIP = -6,           /* a HIP runtime call failed; see pw_last_hip_error() */
+    PW_ERR_CAPTURE = -7,       /* the call would allocate while the stream is being captured */
+    PW_ERR_PLAN_MISMATCH = -8  /* the arguments do not match the plan */
+};
+
+/* Storage types of the six field arrays. */
+enum { PW_F64 = 0, PW_F32 = 1, PW_BF16 = 2, PW_F16 = 3 };
+
+/* Kernel variants (pw_tuning.variant). */
+enum {
+    PW_VARIANT_AUTO = 0,
+    PW_VARIANT_DIRECT = 1, /* one thread per point, every operand loaded through the caches */
+    PW_VARIANT_MARCH = 2   /* workgroup stages y-z plane windows in LDS and marches along x */
+};
+
+/* Shape of one domain: interior extents and element strides (k stride is 1).
+   nx, ny >= 1, nz >= 2.  sy = 0 means nz; sx = 0 means (ny + 2) * sy.
+   Requires sy >= nz and sx >= (ny + 2) * sy. */
+typedef struct pw_shape {
+    int32_t nx, ny, nz;
+    int32_t reserved;  /* must be 0 */
+    int64_t sy, sx;
+} pw_shape;
+
+/* Launch tuning; 0 in any field selects the library default.
+   variant    PW_VARIANT_*.
+   chunk      points of the (j, k) plane one workgroup owns in the march
+              variant (and in the batched kernel): 256, 512 or 1024.
+   seg        x planes one workgroup marches through (>= 1).
+   block      threads per workgroup of the direct variant: 64, 128, 256 or 512.
+   wg_per_cu  resident workgroups per compute unit of the persistent batched
+              launch (1..8; further capped by LDS). */
+typedef struct pw_tuning {
+    int32_t variant;
+    int32_t chunk;
+    int32_t seg;
+    int32_t block;
+    int32_t wg_per_cu;
+} pw_tuning;
+
+/* Per-field power-of-two scales for 16-bit storage (stored = value * scale):
+   in_scale for u, v, w and out_scale for su, sv, sw.  Ignored for PW_F64;
+   NULL means all 1. */
+typedef struct pw_scales {
+    float in_scale[3];
+    float out_scale[3];
+} pw_scales;
+
+/* Opaque plan: storage type, domain shapes and the resolved launch shape.
+   Immutable once created, so one plan may serve concurrent calls on
+   different streams. */
+typedef struct pw_plan pw_plan;
+
+/* Resolved launch description of a plan (for logs and tests). */
+typedef struct pw_plan_info {
+    int32_t storage;
+    int32_t ndomains;
+    int32_t variant;      /* resolved PW_VARIANT_* of domain 0 / of the batched kernel */
+    int32_t chunk;
+    int32_t seg;
+    int32_t block;
+    int64_t workgroups;   /* workgroups of one pw_advect / pw_advect_batched launch */
+    int64_t tiles;        /* (chunk, segment) tiles over all domains */
+    int64_t lds_bytes;    /* dynamic LDS per workgroup */
+    int64_t points;       /* interior grid points over all domains */
+    int64_t batched_workgroups;  /* persistent grid of pw_advect_batched (0 if unavailable) */
+} pw_plan_info;
+
+/* Create a plan for `ndomains` domains (1 for pw_advect; the batch size for
+   pw_advect_batched) of storage type `storage`.
+     plan      host out-pointer; receives the new plan.
+     shapes    host array of ndomains shapes (copied).
+     tuning    host pointer or NULL (library defaults).
+   The plan allocates its small device tile table here, on the current device
+   (the device the plan's launches must run on); this is the only entry point
+   that allocates.  Returns PW_ERR_INVALID_ARG for bad shapes or tuning,
+   PW_ERR_UNSUPPORTED for an unknown storage type or a variant the shape
+   cannot use, PW_ERR_CAPTURE if called while the null stream is capturing,
+   PW_ERR_OUT_OF_MEMORY or PW_ERR_HIP if the table cannot be allocated. */
+int32_t pw_advect_plan(pw_plan **plan, int32_t storage, const pw_shape *shapes,
+                       int32_t ndomains, const pw_tuning *tuning);
+
+/* Free a plan and its device tables.  NULL is accepted.  The caller must make
+   sure no launch that uses the plan is still running. */
+int32_t pw_plan_destroy(pw_plan *plan);
+
+/* Describe a plan; `info` is a host out-pointer. */
+int32_t pw_plan_get_info(const pw_plan *plan, pw_plan_info *info);
+
+/* su, sv, sw of one domain (paper Sec. II-A, Listing 1 for su; the mirror and
+   the staggering rule for sv and sw, as stated at the top of this header).
+     plan             a plan with ndomains == 1 whose storage type the arrays use.
+     u, v, w          device inputs laid out as described above, halos filled.
+     su, sv, sw       device outputs, same shape and strides; must not overlap
+                      any input or each other (PW_ERR_ALIAS): the stencil reads
+                      neighbours, so it cannot run in place.
+     tcx, tcy         horizontal coefficients (host values).
+     tzc1, tzc2       device, nz FP64 values each, entry k-1 for level k
+                      (entries for k = 1 are not read).
+     tzd1, tzd2       device, nz FP64 values each (entries k = 1 and k = nz are
+                      not read).
+     scales           host pointer or NULL; see pw_scales.
+     stream           hipStream_t or NULL.
+   Pointers must be aligned to their element size (PW_ERR_ALIGNMENT); wider
+   vector loads are used when the bases are 16-byte aligned and nz and sx are
+   multiples of the vector width, scalar loads otherwise. */
+int32_t pw_advect(const pw_plan *plan,
+                  const void *u, const void *v, const void *w,
+                  void *su, void *sv, void *sw,
+                  double tcx, double tcy,
+                  const double *tzc1, const double *tzc2,
+                  const double *tzd1, const double *tzd2,
+                  const pw_scales *scales, void *stream);
+
+/* One subdomain of a batched call.  An array of these lives in DEVICE memory
+   (the kernel reads it); its shapes must equal, in order, the shapes the plan
+   was created with (checked on the device: a mismatching domain, or one with
+   a NULL field pointer, is skipped and counted, see pw_plan_error_count).
+   For 16-bit storage a scale of 0 means 1. */
+typedef struct pw_domain_args {
+    pw_shape shape;
+    const void *u, *v, *w;
+    void *su, *sv, *sw;
+    double tcx, tcy;
+    const double *tzc1, *tzc2, *tzd1, *tzd2;
+    pw_scales scales;
+} pw_domain_args;
+
+/* su, sv, sw of all domains of a batched plan in one persistent launch.
+     plan       plan created with the batch's shapes (ndomains > 1 allowed, 1 too).
+     ndomains   must equal the plan's ndomains (PW_ERR_PLAN_MISMATCH).
+     d_args     device array of ndomains pw_domain_args.
+     stream     hipStream_t or NULL.
+   Every domain is computed exactly as pw_advect computes it (same per-point
+   arithmetic), so results are bit-identical to per-domain calls.  Overlap
+   between domains' arrays is not checked. */
+int32_t pw_advect_batched(const pw_plan *plan, int32_t ndomains,
+                          const pw_domain_args *d_args, void *stream);
+
+/* Periodic x-y halo fill of u, v, w of every domain of a plan (asynchronous,
+   no allocation; may be recorded into a graph).  Each halo column (i, j)
+   receives interior column (wrap(i), wrap(j)), wrap(0) = n, wrap(n+1) = 1, so
+   corner columns are periodic too.  Arguments as for pw_advect_batched. */
+int32_t pw_fill_halo_batched(const pw_plan *plan, int32_t ndomains,
+                             const pw_domain_args *d_args, void *stream);
+
+/* Add amplitude * r to every interior point of u and v of every domain, with
+   r uniform in [-1, 1) from a counter-based hash (SplitMix64) of (seed,
+   *d_call, domain, point); then increment *d_call on the device.  Used to
+   change the fields between repeated timestep calls, also inside a replayed
+   graph.  d_call: device pointer to one 64-bit counter owned by the caller.
+   Halos are not refreshed (call pw_fill_halo_batched after). */
+int32_t pw_perturb_batched(const pw_plan *plan, int32_t ndomains,
+                           const pw_domain_args *d_args, uint64_t seed,
+                           unsigned long long *d_call, double amplitude, void *stream);
+
+/* Number of batched-domain records skipped so far because their shape did
+   not match the plan or a field pointer was NULL.  Synchronous (copies one
+   word from the device).  `count` is a host out-pointer. */
+int32_t pw_plan_error_count(const pw_plan *plan, unsigned long long *count);
+
+/* Human-readable name of a status code (static string). */
+const char *pw_status_string(int32_t status);
+
+/* hipError_t behind the last PW_ERR_HIP returned on this host thread (0 if none). */
+int32_t pw_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PW_ADVECT_H */

@@ -1,0 +1,284 @@
+"""ctypes binding of ``libpwadvect.so`` (C ABI: ``include/pw_advect.h``).
+
+Argument marshalling only: torch tensors supply device pointers and
+``torch.cuda`` streams supply hipStream_t handles; every step of the stencil
+runs in the library's HIP kernels.  The library is loaded on first use and
+there is no fallback: if it has not been built, ``lib()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_float, c_int32, c_int64, c_uint64, c_ulonglong, c_void_p
+from typing import Iterable, List, Optional, Sequence
+
+LIBRARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpwadvect.so")
+
+PW_OK = 0
+STATUS_NAMES = {
+    0: "PW_OK", -1: "PW_ERR_INVALID_ARG", -2: "PW_ERR_UNSUPPORTED", -3: "PW_ERR_ALIAS",
+    -4: "PW_ERR_ALIGNMENT", -5: "PW_ERR_OUT_OF_MEMORY", -6: "PW_ERR_HIP", -7: "PW_ERR_CAPTURE",
+    -8: "PW_ERR_PLAN_MISMATCH",
+}
+F64, F32, BF16, F16 = 0, 1, 2, 3
+VARIANT_AUTO, VARIANT_DIRECT, VARIANT_MARCH = 0, 1, 2
+DTYPE_NAMES = {F64: "f64", F32: "f32", BF16: "bf16", F16: "f16"}
+
+
+class PwShape(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("reserved", c_int32),
+                ("sy", c_int64), ("sx", c_int64)]
+
+
+class PwTuning(ctypes.Structure):
+    _fields_ = [("variant", c_int32), ("chunk", c_int32), ("seg", c_int32), ("block", c_int32),
+                ("wg_per_cu", c_int32)]
+
+
+class PwScales(ctypes.Structure):
+    _fields_ = [("in_scale", c_float * 3), ("out_scale", c_float * 3)]
+
+
+class PwPlanInfo(ctypes.Structure):
+    _fields_ = [("storage", c_int32), ("ndomains", c_int32), ("variant", c_int32), ("chunk", c_int32),
+                ("seg", c_int32), ("block", c_int32), ("workgroups", c_int64), ("tiles", c_int64),
+                ("lds_bytes", c_int64), ("points", c_int64), ("batched_workgroups", c_int64)]
+
+
+class PwDomainArgs(ctypes.Structure):
+    _fields_ = [("shape", PwShape),
+                ("u", c_void_p), ("v", c_void_p), ("w", c_void_p),
+                ("su", c_void_p), ("sv", c_void_p), ("sw", c_void_p),
+                ("tcx", c_double), ("tcy", c_double),
+                ("tzc1", c_void_p), ("tzc2", c_void_p), ("tzd1", c_void_p), ("tzd2", c_void_p),
+                ("scales", PwScales)]
+
+
+#: every function the header declares, with (restype, argtypes)
+SIGNATURES = {
+    "pw_advect_plan": (c_int32, [POINTER(c_void_p), c_int32, POINTER(PwShape), c_int32, POINTER(PwTuning)]),
+    "pw_plan_destroy": (c_int32, [c_void_p]),
+    "pw_plan_get_info": (c_int32, [c_void_p, POINTER(PwPlanInfo)]),
+    "pw_advect": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                            c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p,
+                            POINTER(PwScales), c_void_p]),
+    "pw_advect_batched": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "pw_fill_halo_batched": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "pw_perturb_batched": (c_int32, [c_void_p, c_int32, c_void_p, c_uint64, c_void_p, c_double, c_void_p]),
+    "pw_plan_error_count": (c_int32, [c_void_p, POINTER(c_ulonglong)]),
+    "pw_status_string": (ctypes.c_char_p, [c_int32]),
+    "pw_last_hip_error": (c_int32, []),
+}
+
+_lib = None
+
+
+class PwError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        hip = _lib.pw_last_hip_error() if (_lib is not None and status == -6) else 0
+        self.hip_error = hip
+        msg = "%s failed: %s (%s)" % (where, STATUS_NAMES.get(status, status),
+                                      _lib.pw_status_string(status).decode() if _lib else "?")
+        if hip:
+            msg += ", hipError %d" % hip
+        super().__init__(msg)
+
+
+def lib(path: Optional[str] = None):
+    """Load the HIP library (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIBRARY
+    if not os.path.exists(p):
+        raise FileNotFoundError(
+            "HIP library %s is not built; run `python -m paper_2107_13500_amd.build` "
+            "(or __graft_entry__.build())" % p)
+    l = ctypes.CDLL(p)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(l, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = l
+    return l
+
+
+def check(status: int, where: str):
+    if status != PW_OK:
+        raise PwError(status, where)
+
+
+# ----------------------------------------------------------------------------
+# torch plumbing (memory and streams only)
+# ----------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def storage_of(dtype) -> int:
+    torch = _torch()
+    table = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16}
+    if dtype not in table:
+        raise TypeError("unsupported field dtype %s" % dtype)
+    return table[dtype]
+
+
+def torch_dtype(storage: int):
+    torch = _torch()
+    return {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16, F16: torch.float16}[storage]
+
+
+def stream_handle(stream=None) -> int:
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def shape_of(t) -> PwShape:
+    """pw_shape of a halo'd field tensor (nx+2, ny+2, nz) with a unit k stride."""
+    if t.dim() != 3 or t.stride(2) != 1:
+        raise ValueError("fields must be (nx+2, ny+2, nz) tensors with a contiguous k axis")
+    return PwShape(t.shape[0] - 2, t.shape[1] - 2, t.shape[2], 0, t.stride(1), t.stride(0))
+
+
+def make_tuning(tuning=None) -> Optional[PwTuning]:
+    if tuning is None:
+        return None
+    if isinstance(tuning, PwTuning):
+        return tuning
+    return PwTuning(int(tuning.get("variant", 0)), int(tuning.get("chunk", 0)), int(tuning.get("seg", 0)),
+                    int(tuning.get("block", 0)), int(tuning.get("wg_per_cu", 0)))
+
+
+def make_scales(in_scale=(1.0, 1.0, 1.0), out_scale=(1.0, 1.0, 1.0)) -> PwScales:
+    s = PwScales()
+    for f in range(3):
+        s.in_scale[f] = float(in_scale[f])
+        s.out_scale[f] = float(out_scale[f])
+    return s
+
+
+class Plan:
+    """Owning wrapper of a pw_plan."""
+
+    def __init__(self, storage: int, shapes: Sequence[PwShape], tuning=None):
+        l = lib()
+        arr = (PwShape * len(shapes))(*shapes)
+        h = c_void_p()
+        t = make_tuning(tuning)
+        check(l.pw_advect_plan(ctypes.byref(h), int(storage), arr, len(shapes),
+                               ctypes.byref(t) if t is not None else None), "pw_advect_plan")
+        self.handle = h
+        self.storage = storage
+        self.ndomains = len(shapes)
+        self.shapes = list(shapes)
+
+    def info(self) -> dict:
+        i = PwPlanInfo()
+        check(lib().pw_plan_get_info(self.handle, ctypes.byref(i)), "pw_plan_get_info")
+        return {f: getattr(i, f) for f, _ in PwPlanInfo._fields_}
+
+    def error_count(self) -> int:
+        n = c_ulonglong(0)
+        check(lib().pw_plan_error_count(self.handle, ctypes.byref(n)), "pw_plan_error_count")
+        return int(n.value)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            check(lib().pw_plan_destroy(self.handle), "pw_plan_destroy")
+            self.handle = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def advect(plan: Plan, u, v, w, su, sv, sw, tcx: float, tcy: float, tzc1, tzc2, tzd1, tzd2,
+           scales: Optional[PwScales] = None, stream=None) -> None:
+    """pw_advect on torch device tensors (asynchronous on `stream`)."""
+    st = lib().pw_advect(plan.handle, u.data_ptr(), v.data_ptr(), w.data_ptr(),
+                         su.data_ptr(), sv.data_ptr(), sw.data_ptr(), float(tcx), float(tcy),
+                         tzc1.data_ptr(), tzc2.data_ptr(), tzd1.data_ptr(), tzd2.data_ptr(),
+                         ctypes.byref(scales) if scales is not None else None, stream_handle(stream))
+    check(st, "pw_advect")
+
+
+def advect_batched(plan: Plan, d_args, stream=None) -> None:
+    """pw_advect_batched; ``d_args`` is a uint8 device tensor holding the pw_domain_args array."""
+    check(lib().pw_advect_batched(plan.handle, plan.ndomains, d_args.data_ptr(), stream_handle(stream)),
+          "pw_advect_batched")
+
+
+def fill_halo_batched(plan: Plan, d_args, stream=None) -> None:
+    check(lib().pw_fill_halo_batched(plan.handle, plan.ndomains, d_args.data_ptr(), stream_handle(stream)),
+          "pw_fill_halo_batched")
+
+
+def perturb_batched(plan: Plan, d_args, seed: int, d_call, amplitude: float, stream=None) -> None:
+    check(lib().pw_perturb_batched(plan.handle, plan.ndomains, d_args.data_ptr(), int(seed),
+                                   d_call.data_ptr(), float(amplitude), stream_handle(stream)),
+          "pw_perturb_batched")
+
+
+def domain_args_tensor(records: Sequence[PwDomainArgs], device):
+    """Copy an array of pw_domain_args to a device uint8 tensor (synchronous)."""
+    torch = _torch()
+    arr = (PwDomainArgs * len(records))(*records)
+    raw = bytes(memoryview(arr).cast("B"))
+    host = torch.frombuffer(bytearray(raw), dtype=torch.uint8)
+    return host.to(device)
+
+
+def domain_record(u, v, w, su, sv, sw, tcx, tcy, tzc1, tzc2, tzd1, tzd2,
+                  scales: Optional[PwScales] = None) -> PwDomainArgs:
+    r = PwDomainArgs()
+    r.shape = shape_of(u)
+    r.u, r.v, r.w = u.data_ptr(), v.data_ptr(), w.data_ptr()
+    r.su, r.sv, r.sw = su.data_ptr(), sv.data_ptr(), sw.data_ptr()
+    r.tcx, r.tcy = float(tcx), float(tcy)
+    r.tzc1, r.tzc2, r.tzd1, r.tzd2 = tzc1.data_ptr(), tzc2.data_ptr(), tzd1.data_ptr(), tzd2.data_ptr()
+    r.scales = scales if scales is not None else make_scales()
+    return r
+
+
+# ----------------------------------------------------------------------------
+# convenience: one domain, fields already on the device
+# ----------------------------------------------------------------------------
+class DeviceDomain:
+    """Device copies of one domain's fields and coefficients plus output buffers.
+
+    ``u, v, w`` are (nx+2, ny+2, nz) tensors of the storage dtype; the four
+    coefficient arrays stay float64 (the ABI keeps them FP64 for every
+    storage type).  Outputs start zeroed so their (never written) halos are 0.
+    """
+
+    def __init__(self, u, v, w, tcx, tcy, tzc1, tzc2, tzd1, tzd2, scales: Optional[PwScales] = None):
+        torch = _torch()
+        self.u, self.v, self.w = u, v, w
+        self.su, self.sv, self.sw = (torch.zeros_like(u) for _ in range(3))
+        self.tcx, self.tcy = float(tcx), float(tcy)
+        self.tz = [t.to(device=u.device, dtype=torch.float64).contiguous() for t in (tzc1, tzc2, tzd1, tzd2)]
+        self.scales = scales
+
+    @property
+    def outputs(self):
+        return self.su, self.sv, self.sw
+
+    def record(self) -> PwDomainArgs:
+        return domain_record(self.u, self.v, self.w, self.su, self.sv, self.sw, self.tcx, self.tcy,
+                             *self.tz, scales=self.scales)
+
+    def run(self, plan: Plan, stream=None):
+        advect(plan, self.u, self.v, self.w, self.su, self.sv, self.sw, self.tcx, self.tcy, *self.tz,
+               scales=self.scales, stream=stream)

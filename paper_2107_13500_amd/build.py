@@ -1,0 +1,69 @@
+"""Build the HIP library ``libpwadvect.so`` for gfx950 with hipcc.
+
+    python -m paper_2107_13500_amd.build
+
+Compiles every source under ``csrc/`` into one shared library next to this
+file.  Flags: ``-O3``; packed FP32 instructions disabled (hand-written code
+never uses them and the compiler must not form them either); no fast-math.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+import tempfile
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIBRARY = os.path.join(HERE, "libpwadvect.so")
+SOURCES = ["pw_advect.hip", "pw_batched.hip", "pw_tune.hip"]
+ARCH = "gfx950"
+
+HIPCC_FLAGS = [
+    "--offload-arch=" + ARCH,
+    "-O3",
+    "-std=c++17",
+    "-fPIC",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall",
+    "-I", INCLUDE,
+    "-I", CSRC,
+]
+
+
+def hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def build(verbose: bool = False, extra=()) -> str:
+    """Compile all sources and link ``libpwadvect.so`` (always rebuilds)."""
+    cc = hipcc()
+    with tempfile.TemporaryDirectory(prefix="pwadv_build_") as tmp:
+        objs = []
+        for src in SOURCES:
+            path = os.path.join(CSRC, src)
+            if not os.path.exists(path):
+                continue
+            obj = os.path.join(tmp, os.path.splitext(src)[0] + ".o")
+            cmd = [cc, *HIPCC_FLAGS, *extra, "-c", path, "-o", obj]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            subprocess.run(cmd, check=True)
+            objs.append(obj)
+        out_tmp = LIBRARY + ".tmp%d" % os.getpid()
+        cmd = [cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", out_tmp]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(out_tmp, LIBRARY)
+    return LIBRARY
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,402 @@
+// Batched PW advection: many uneven subdomains in one persistent launch, plus
+// the periodic halo fill and the field perturbation used between repeated
+// timestep calls.
+//
+// The plan flattens every domain's (chunk, segment) tiles into one global
+// tile range (prefix sums in a device table).  A persistent grid sized to the
+// GPU walks that range; each workgroup maps a tile to its domain by binary
+// search and runs exactly the per-tile code of the single-domain march
+// kernel, so each domain's result is bit-identical to a pw_advect call with
+// the same chunk and segment shape.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <mutex>
+#include <vector>
+
+#include "pw_plan.hpp"
+
+namespace pw {
+
+namespace {
+
+__device__ __forceinline__ bool shape_matches(const pw_shape& a, const BatchDomain& b) {
+    const int64_t sy = a.sy ? a.sy : a.nz;
+    const int64_t sx = a.sx ? a.sx : (int64_t)(a.ny + 2) * sy;
+    return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.reserved == 0 && sy == b.sy && sx == b.sx;
+}
+
+__device__ __forceinline__ float inv_or_one(float s) { return s > 0.0f ? 1.0f / s : 1.0f; }
+__device__ __forceinline__ float scale_or_one(float s) { return s > 0.0f ? s : 1.0f; }
+
+template <typename ST>
+__device__ __forceinline__ DomainArgs domain_from(const pw_domain_args& a, const BatchDomain& b) {
+    DomainArgs d{};
+    d.u = a.u;
+    d.v = a.v;
+    d.w = a.w;
+    d.su = a.su;
+    d.sv = a.sv;
+    d.sw = a.sw;
+    d.tzc1 = a.tzc1;
+    d.tzc2 = a.tzc2;
+    d.tzd1 = a.tzd1;
+    d.tzd2 = a.tzd2;
+    d.tcx = a.tcx;
+    d.tcy = a.tcy;
+    for (int f = 0; f < 3; ++f) {
+        d.in_inv[f] = is16<ST>::value ? inv_or_one(a.scales.in_scale[f]) : 1.0f;
+        d.out_scale[f] = is16<ST>::value ? scale_or_one(a.scales.out_scale[f]) : 1.0f;
+    }
+    d.nx = b.nx;
+    d.ny = b.ny;
+    d.nz = b.nz;
+    d.sy = b.sy;
+    d.sx = b.sx;
+    return d;
+}
+
+__device__ __forceinline__ int find_domain(const BatchDomain* table, int ndom, int64_t t) {
+    int lo = 0, hi = ndom - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (table[mid].tile_begin <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+template <typename ST, int NT, int P>
+__global__ __launch_bounds__(NT) void pw_batched_kernel(const BatchDomain* __restrict__ table, int ndom,
+                                                        int64_t ntiles, const pw_domain_args* __restrict__ args,
+                                                        int seg, int wpad, unsigned long long* errors,
+                                                        int vec_shapes) {
+    using CT = typename compute_of<ST>::type;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    CT* lds = reinterpret_cast<CT*>(smem_raw);
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int dom = find_domain(table, ndom, t);
+        const BatchDomain b = table[dom];
+        const int64_t local = t - b.tile_begin;
+        const int c = (int)(local % b.nchunks);
+        const int s = (int)(local / b.nchunks);
+        const pw_domain_args& a = args[dom];
+        if (!shape_matches(a.shape, b) || !a.u || !a.v || !a.w || !a.su || !a.sv || !a.sw) {
+            if (threadIdx.x == 0 && local == 0) atomicAdd(errors, 1ull);
+            continue;   // uniform over the workgroup
+        }
+        const DomainArgs d = domain_from<ST>(a, b);
+        const int i_begin = 1 + s * seg;
+        const int i_end = min(i_begin + seg - 1, b.nx);
+        const bool vec = vec_shapes && aligned16(a.u) && aligned16(a.v) && aligned16(a.w) && aligned16(a.su) &&
+                         aligned16(a.sv) && aligned16(a.sw);
+        if (vec) march_tile<ST, NT, P, true>(d, c, i_begin, i_end, wpad, lds);
+        else march_tile<ST, NT, P, false>(d, c, i_begin, i_end, wpad, lds);
+    }
+}
+
+// Periodic x-y halo of u, v, w.  Each halo column (i, j) copies interior
+// column (wrap(i), wrap(j)) with wrap(0) = n, wrap(n + 1) = 1 -- the same
+// result as filling x faces first and then y faces over the halo'd x range.
+// grid: x over halo elements of the largest domain, y over domains.
+template <typename ST>
+__global__ __launch_bounds__(256) void pw_halo_kernel(const BatchDomain* __restrict__ table,
+                                                      const pw_domain_args* __restrict__ args) {
+    const int dom = blockIdx.y;
+    const BatchDomain b = table[dom];
+    const pw_domain_args& a = args[dom];
+    if (!shape_matches(a.shape, b)) return;
+    const int nhalo = 2 * (b.nx + 2) + 2 * b.ny;
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= (int64_t)nhalo * b.nz) return;
+    const int k = (int)(g % b.nz);
+    const int h = (int)(g / b.nz);
+    int i, j;
+    if (h < b.nx + 2) {
+        i = h;
+        j = 0;
+    } else if (h < 2 * (b.nx + 2)) {
+        i = h - (b.nx + 2);
+        j = b.ny + 1;
+    } else if (h < 2 * (b.nx + 2) + b.ny) {
+        i = 0;
+        j = 1 + h - 2 * (b.nx + 2);
+    } else {
+        i = b.nx + 1;
+        j = 1 + h - 2 * (b.nx + 2) - b.ny;
+    }
+    const int si = i == 0 ? b.nx : (i == b.nx + 1 ? 1 : i);
+    const int sj = j == 0 ? b.ny : (j == b.ny + 1 ? 1 : j);
+    const int64_t dst = k + (int64_t)j * b.sy + (int64_t)i * b.sx;
+    const int64_t src = k + (int64_t)sj * b.sy + (int64_t)si * b.sx;
+    ST* f[3] = {(ST*)a.u, (ST*)a.v, (ST*)a.w};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) f[q][dst] = f[q][src];
+}
+
+// SplitMix64 finaliser (Steele, Lea and Flood, OOPSLA 2014).
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+    x += 0x9e3779b97f4a7c15ull;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
+}
+
+// u += amp * r, v += amp * r' on the interior, r uniform in [-1, 1) from a
+// counter-based hash of (seed, call, domain, field, point); `call` is read
+// from device memory so a captured graph perturbs differently on each replay.
+template <typename ST>
+__global__ __launch_bounds__(256) void pw_perturb_kernel(const BatchDomain* __restrict__ table,
+                                                         const pw_domain_args* __restrict__ args, uint64_t seed,
+                                                         const unsigned long long* __restrict__ call, double amp) {
+    using CT = typename compute_of<ST>::type;
+    const int dom = blockIdx.y;
+    const BatchDomain b = table[dom];
+    const pw_domain_args& a = args[dom];
+    if (!shape_matches(a.shape, b)) return;
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t npts = (int64_t)b.nx * b.ny * b.nz;
+    if (g >= npts) return;
+    const int k = (int)(g % b.nz);
+    const int64_t col = g / b.nz;
+    const int j = (int)(col % b.ny) + 1;
+    const int i = (int)(col / b.ny) + 1;
+    const int64_t o = k + (int64_t)j * b.sy + (int64_t)i * b.sx;
+    const uint64_t key = splitmix64(seed ^ splitmix64((uint64_t)(*call) * 0x100000001b3ull + (uint64_t)dom));
+    ST* f[2] = {(ST*)a.u, (ST*)a.v};
+    const float sc[2] = {is16<ST>::value ? scale_or_one(a.scales.in_scale[0]) : 1.0f,
+                         is16<ST>::value ? scale_or_one(a.scales.in_scale[1]) : 1.0f};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const uint64_t h = splitmix64(key + (uint64_t)(2 * g + q));
+        const double r = (double)(h >> 11) * 0x1.0p-52 - 1.0;   // [-1, 1)
+        CT x = to_compute(f[q][o]);
+        x += static_cast<CT>(amp * r) * static_cast<CT>(sc[q]);
+        f[q][o] = from_compute<ST>(x);
+    }
+}
+
+__global__ void pw_bump_kernel(unsigned long long* call) { *call += 1ull; }
+
+template <typename ST, int P>
+hipError_t launch_batched(const pw_plan* p, const pw_domain_args* args, hipStream_t stream) {
+    const BatchState& B = p->batch;
+    auto kern = pw_batched_kernel<ST, 256, P>;
+    static std::once_flag once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(once, [&] {
+        attr_err = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    });
+    if (attr_err != hipSuccess) return attr_err;
+    hipLaunchKernelGGL(kern, dim3((unsigned)B.launch.workgroups), dim3(256), (size_t)B.launch.lds_bytes, stream,
+                       B.d_table, p->ndomains, B.launch.tiles, args, B.launch.seg, B.launch.wpad, B.d_errors,
+                       B.vec_shapes ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <typename ST>
+hipError_t dispatch_batched(const pw_plan* p, const pw_domain_args* args, hipStream_t stream) {
+    switch (p->batch.launch.chunk) {
+        case 256: return launch_batched<ST, 256>(p, args, stream);
+        case 512: return launch_batched<ST, 512>(p, args, stream);
+        case 1024: return launch_batched<ST, 1024>(p, args, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int64_t max_halo_elems(const pw_plan* p) {
+    int64_t m = 0;
+    for (const pw_shape& s : p->shapes) m = std::max<int64_t>(m, (int64_t)(2 * (s.nx + 2) + 2 * s.ny) * s.nz);
+    return m;
+}
+
+int64_t max_points(const pw_plan* p) {
+    int64_t m = 0;
+    for (const pw_shape& s : p->shapes) m = std::max<int64_t>(m, (int64_t)s.nx * s.ny * s.nz);
+    return m;
+}
+
+}  // namespace
+
+int32_t batched_plan_init(pw_plan* p) {
+    BatchState& B = p->batch;
+    for (const pw_shape& s : p->shapes) {
+        if (!march_possible(s)) return PW_OK;   // batched entry points will report PW_ERR_UNSUPPORTED
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(nullptr, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return PW_ERR_CAPTURE;
+
+    const pw_tuning& t = p->tuning;
+    const int32_t chunk = t.chunk ? t.chunk : 512;
+    if (chunk != 256 && chunk != 512 && chunk != 1024) return PW_ERR_INVALID_ARG;
+    if (t.seg < 0 || t.wg_per_cu < 0 || t.wg_per_cu > 8) return PW_ERR_INVALID_ARG;
+    int32_t nzmax = 0;
+    for (const pw_shape& s : p->shapes) nzmax = std::max(nzmax, s.nz);
+
+    std::vector<BatchDomain> table(p->ndomains);
+    int64_t tiles = 0;
+    bool vec = true;
+    const int64_t vw = 16 / elem_bytes(p->storage);
+    int32_t seg_used = 0;
+    for (int32_t d = 0; d < p->ndomains; ++d) {
+        const pw_shape& s = p->shapes[d];
+        BatchDomain& b = table[d];
+        b.nx = s.nx;
+        b.ny = s.ny;
+        b.nz = s.nz;
+        b.sy = s.sy;
+        b.sx = s.sx;
+        b.pad_ = 0;
+        b.nchunks = (int32_t)(((int64_t)s.ny * s.nz + chunk - 1) / chunk);
+        // one segment length for the whole batch (the kernel takes one);
+        // the tuner may pick it, otherwise whole domains up to 64 planes
+        const int32_t seg = t.seg ? t.seg : 64;
+        seg_used = seg;
+        b.nseg = (s.nx + seg - 1) / seg;
+        b.tile_begin = tiles;
+        tiles += (int64_t)b.nchunks * b.nseg;
+        if (s.nz % vw || s.sx % vw || s.sy % vw) vec = false;
+    }
+    Launch L{};
+    L.variant = PW_VARIANT_MARCH;
+    L.chunk = chunk;
+    L.seg = seg_used;
+    L.block = 256;
+    L.wpad = ((chunk + 2 * nzmax) + 3) / 4 * 4;
+    L.lds_bytes = 9 * (int64_t)L.wpad * compute_bytes(p->storage);
+    L.tiles = tiles;
+
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return report_hip(e);
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return report_hip(e);
+    const int64_t by_lds = std::max<int64_t>(1, (160 * 1024) / std::max<int64_t>(L.lds_bytes, 1));
+    int64_t per_cu = std::min<int64_t>(by_lds, 8);
+    if (t.wg_per_cu > 0) per_cu = std::min<int64_t>(per_cu, t.wg_per_cu);
+    L.workgroups = std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)prop.multiProcessorCount * per_cu));
+    L.nchunks = 0;
+    L.nseg = 0;
+
+    void* mem = nullptr;
+    const size_t tbytes = sizeof(BatchDomain) * table.size();
+    e = hipMalloc(&mem, tbytes + 64);
+    if (e == hipErrorOutOfMemory) return PW_ERR_OUT_OF_MEMORY;
+    if (e != hipSuccess) return report_hip(e);
+    B.d_table = static_cast<BatchDomain*>(mem);
+    B.d_errors = reinterpret_cast<unsigned long long*>(static_cast<char*>(mem) + ((tbytes + 15) / 16) * 16);
+    e = hipMemcpy(B.d_table, table.data(), tbytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(B.d_errors, 0, sizeof(unsigned long long));
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        B.d_table = nullptr;
+        B.d_errors = nullptr;
+        return report_hip(e);
+    }
+    B.launch = L;
+    B.device = dev;
+    B.vec_shapes = vec;
+    return PW_OK;
+}
+
+int32_t batched_plan_free(pw_plan* p) {
+    if (p->batch.d_table) {
+        hipError_t e = hipFree(p->batch.d_table);
+        p->batch.d_table = nullptr;
+        p->batch.d_errors = nullptr;
+        if (e != hipSuccess) return report_hip(e);
+    }
+    return PW_OK;
+}
+
+}  // namespace pw
+
+using namespace pw;
+
+extern "C" {
+
+int32_t pw_advect_batched(const pw_plan* plan, int32_t ndomains, const pw_domain_args* d_args, void* stream) {
+    if (!plan || !d_args) return PW_ERR_INVALID_ARG;
+    if (ndomains != plan->ndomains) return PW_ERR_PLAN_MISMATCH;
+    if (!plan->batch.d_table) return PW_ERR_UNSUPPORTED;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    switch (plan->storage) {
+        case PW_F64: e = dispatch_batched<double>(plan, d_args, s); break;
+        case PW_F32: e = dispatch_batched<float>(plan, d_args, s); break;
+        case PW_BF16: e = dispatch_batched<bf16_t>(plan, d_args, s); break;
+        case PW_F16: e = dispatch_batched<f16_t>(plan, d_args, s); break;
+        default: return PW_ERR_UNSUPPORTED;
+    }
+    if (e != hipSuccess) return report_hip(e);
+    return PW_OK;
+}
+
+int32_t pw_fill_halo_batched(const pw_plan* plan, int32_t ndomains, const pw_domain_args* d_args, void* stream) {
+    if (!plan || !d_args) return PW_ERR_INVALID_ARG;
+    if (ndomains != plan->ndomains) return PW_ERR_PLAN_MISMATCH;
+    if (!plan->batch.d_table) return PW_ERR_UNSUPPORTED;
+    const int64_t blocks = (max_halo_elems(plan) + 255) / 256;
+    dim3 grid((unsigned)blocks, (unsigned)ndomains);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const BatchDomain* tb = plan->batch.d_table;
+    switch (plan->storage) {
+        case PW_F64: hipLaunchKernelGGL(pw_halo_kernel<double>, grid, dim3(256), 0, s, tb, d_args); break;
+        case PW_F32: hipLaunchKernelGGL(pw_halo_kernel<float>, grid, dim3(256), 0, s, tb, d_args); break;
+        case PW_BF16: hipLaunchKernelGGL(pw_halo_kernel<bf16_t>, grid, dim3(256), 0, s, tb, d_args); break;
+        case PW_F16: hipLaunchKernelGGL(pw_halo_kernel<f16_t>, grid, dim3(256), 0, s, tb, d_args); break;
+        default: return PW_ERR_UNSUPPORTED;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return report_hip(e);
+    return PW_OK;
+}
+
+int32_t pw_perturb_batched(const pw_plan* plan, int32_t ndomains, const pw_domain_args* d_args, uint64_t seed,
+                           unsigned long long* d_call, double amplitude, void* stream) {
+    if (!plan || !d_args || !d_call || !std::isfinite(amplitude)) return PW_ERR_INVALID_ARG;
+    if (ndomains != plan->ndomains) return PW_ERR_PLAN_MISMATCH;
+    if (!plan->batch.d_table) return PW_ERR_UNSUPPORTED;
+    const int64_t blocks = (max_points(plan) + 255) / 256;
+    dim3 grid((unsigned)blocks, (unsigned)ndomains);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const BatchDomain* tb = plan->batch.d_table;
+    switch (plan->storage) {
+        case PW_F64:
+            hipLaunchKernelGGL(pw_perturb_kernel<double>, grid, dim3(256), 0, s, tb, d_args, seed, d_call, amplitude);
+            break;
+        case PW_F32:
+            hipLaunchKernelGGL(pw_perturb_kernel<float>, grid, dim3(256), 0, s, tb, d_args, seed, d_call, amplitude);
+            break;
+        case PW_BF16:
+            hipLaunchKernelGGL(pw_perturb_kernel<bf16_t>, grid, dim3(256), 0, s, tb, d_args, seed, d_call, amplitude);
+            break;
+        case PW_F16:
+            hipLaunchKernelGGL(pw_perturb_kernel<f16_t>, grid, dim3(256), 0, s, tb, d_args, seed, d_call, amplitude);
+            break;
+        default: return PW_ERR_UNSUPPORTED;
+    }
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(pw_bump_kernel, dim3(1), dim3(1), 0, s, d_call);
+        e = hipGetLastError();
+    }
+    if (e != hipSuccess) return report_hip(e);
+    return PW_OK;
+}
+
+int32_t pw_plan_error_count(const pw_plan* plan, unsigned long long* count) {
+    if (!plan || !count) return PW_ERR_INVALID_ARG;
+    *count = 0;
+    if (!plan->batch.d_errors) return PW_OK;
+    hipError_t e = hipMemcpy(count, plan->batch.d_errors, sizeof(unsigned long long), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return report_hip(e);
+    return PW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,69 @@
+// Storage types, conversions and the compensated product difference used by
+// the PW advection kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pw {
+
+// bfloat16 stored as its raw 16 bits; FP16 as the compiler's _Float16.
+struct bf16_t {
+    uint16_t bits;
+};
+using f16_t = _Float16;
+
+// ---------------------------------------------------------------------------
+// compute type of each storage type
+// ---------------------------------------------------------------------------
+template <typename ST> struct compute_of { using type = float; };
+template <> struct compute_of<double> { using type = double; };
+
+// ---------------------------------------------------------------------------
+// storage -> compute
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double to_compute(double x) { return x; }
+__device__ __forceinline__ float to_compute(float x) { return x; }
+__device__ __forceinline__ float to_compute(f16_t x) { return static_cast<float>(x); }
+__device__ __forceinline__ float to_compute(bf16_t x) {
+    return __uint_as_float(static_cast<uint32_t>(x.bits) << 16);
+}
+
+// ---------------------------------------------------------------------------
+// compute -> storage (round to nearest even)
+// ---------------------------------------------------------------------------
+template <typename ST> __device__ __forceinline__ ST from_compute(typename compute_of<ST>::type x);
+template <> __device__ __forceinline__ double from_compute<double>(double x) { return x; }
+template <> __device__ __forceinline__ float from_compute<float>(float x) { return x; }
+template <> __device__ __forceinline__ f16_t from_compute<f16_t>(float x) { return static_cast<f16_t>(x); }
+template <> __device__ __forceinline__ bf16_t from_compute<bf16_t>(float x) {
+    uint32_t u = __float_as_uint(x);
+    bf16_t r;
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) {
+        r.bits = static_cast<uint16_t>((u >> 16) | 0x0040u);   // quiet NaN, sign kept
+    } else {
+        u += 0x7fffu + ((u >> 16) & 1u);                          // ties to even
+        r.bits = static_cast<uint16_t>(u >> 16);
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// a*b - c*d
+// ---------------------------------------------------------------------------
+// FP64: plain expression (the compiler may fuse; parity is judged by norm).
+__device__ __forceinline__ double pdiff(double a, double b, double c, double d) {
+    return a * b - c * d;
+}
+
+// FP32: Kahan's algorithm with fused multiply-adds (Jeannerod, Louvet and
+// Muller, Math. Comp. 82 (2013), error <= 2 ulp of the exact result):
+// w = RN(c d); e = c d - w exactly; f = RN(a b - w); result RN(f - e).
+__device__ __forceinline__ float pdiff(float a, float b, float c, float d) {
+    float w = c * d;
+    float e = __builtin_fmaf(c, d, -w);
+    float f = __builtin_fmaf(a, b, -w);
+    return f - e;
+}
+
+}  // namespace pw

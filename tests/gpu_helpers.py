@@ -1,0 +1,66 @@
+"""Helpers for the GPU tests: seeded problems on the device, comparison with the oracle."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import torch
+
+import oracle
+from paper_2107_13500_amd import binding as B
+from paper_2107_13500_amd import inputs
+
+DEV = "cuda:0"
+F64_TOL = 1e-12          # max-norm relative, per field
+
+SENTINEL = {torch.float64: -7.25e300, torch.float32: -7.25e30, torch.bfloat16: -7.25e30, torch.float16: -6.0e4}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def to_storage(a: np.ndarray, dtype, scale: float = 1.0):
+    t = torch.from_numpy(a * scale if scale != 1.0 else a)
+    return t.to(dtype)
+
+
+def device_domain(p: inputs.Problem, storage: int = B.F64, scales=None, sentinel=True):
+    dt = B.torch_dtype(storage)
+    ins = (1.0, 1.0, 1.0) if scales is None else tuple(scales.in_scale)
+    u, v, w = (to_storage(a, dt, s).to(DEV) for a, s in zip((p.u, p.v, p.w), ins))
+    c = p.coeffs
+    tz = [torch.from_numpy(x).to(DEV) for x in c.arrays()]
+    d = B.DeviceDomain(u, v, w, c.tcx, c.tcy, *tz, scales=scales)
+    if sentinel:
+        for o in d.outputs:
+            o.fill_(SENTINEL[dt])
+    return d
+
+
+def max_rel(g: np.ndarray, o: np.ndarray) -> float:
+    den = np.max(np.abs(o))
+    return float(np.max(np.abs(g - o)) / den) if den > 0 else float(np.max(np.abs(g)))
+
+
+def check_halo_untouched(d: B.DeviceDomain):
+    dt = d.su.dtype
+    for o in d.outputs:
+        for face in (o[0], o[-1], o[:, 0], o[:, -1]):
+            assert torch.all(face == SENTINEL[dt]).item(), "an output halo column was written"
+
+
+def compare_f64(d: B.DeviceDomain, ref, tol: float = F64_TOL, where: str = ""):
+    """Element-wise comparison of the device outputs with oracle outputs."""
+    errs = []
+    for name, g_t, o in zip(("su", "sv", "sw"), d.outputs, ref):
+        g = g_t.cpu().numpy()
+        gi, oi = g[1:-1, 1:-1], o[1:-1, 1:-1]
+        assert np.all(gi[:, :, 0] == 0.0), "%s %s: k = 1 must be exactly 0" % (where, name)
+        if name == "sw":
+            assert np.all(gi[:, :, -1] == 0.0), "%s: sw(nz) must be exactly 0" % where
+        e = max_rel(gi, oi)
+        errs.append(e)
+        assert e <= tol, "%s %s: max-norm relative error %.3e > %.1e" % (where, name, e, tol)
+    return errs

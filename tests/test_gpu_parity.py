@@ -1,0 +1,124 @@
+"""FP64 parity of the HIP kernels with the CPU oracle, through the C ABI (GPU).
+
+Criterion (per field): max |gpu - oracle| / max |oracle| over the computed
+points <= 1e-12; level k = 1 and sw(nz) exactly 0; output halo columns never
+written (they keep a sentinel).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import DEV, check_halo_untouched, compare_f64, device_domain, say
+from paper_2107_13500_amd import binding as B
+from paper_2107_13500_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [
+    (1, 1, 2), (2, 3, 3), (3, 5, 4), (7, 13, 63), (33, 17, 65), (20, 9, 96),
+    (11, 7, 127), (9, 5, 128), (5, 3, 256), (64, 64, 64), (37, 29, 64),
+]
+TUNINGS = [
+    {"variant": B.VARIANT_DIRECT},
+    {"variant": B.VARIANT_MARCH, "chunk": 256, "seg": 1},
+    {"variant": B.VARIANT_MARCH, "chunk": 512, "seg": 3},
+    {"variant": B.VARIANT_MARCH, "chunk": 1024, "seg": 64},
+    {},
+]
+
+
+def _run(p, tuning, storage=B.F64):
+    d = device_domain(p, storage)
+    plan = B.Plan(storage, [B.shape_of(d.u)], tuning)
+    d.run(plan)
+    torch.cuda.synchronize()
+    return d, plan
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("tuning", TUNINGS, ids=["direct", "m256s1", "m512s3", "m1024s64", "auto"])
+def test_f64_parity_shapes(shape, tuning):
+    nx, ny, nz = shape
+    say("parity", shape, tuning)
+    p = inputs.make_problem(nx, ny, nz, seed=1000 + nx * 7 + ny * 3 + nz)
+    ref = oracle.advect_problem(p)
+    d, plan = _run(p, tuning)
+    compare_f64(d, ref, where="%s %s" % (shape, tuning))
+    check_halo_untouched(d)
+
+
+def test_f64_parity_pw64_all_points():
+    p = inputs.workload("pw64")
+    ref = oracle.advect_problem(p)
+    d, plan = _run(p, {})
+    info = plan.info()
+    say("pw64 plan", info)
+    assert info["variant"] == B.VARIANT_MARCH
+    compare_f64(d, ref, where="pw64")
+    check_halo_untouched(d)
+
+
+def test_f64_parity_pw512_all_points():
+    p = inputs.workload("pw512")
+    ref = oracle.advect_problem(p, threads=8)
+    d, plan = _run(p, {})
+    errs = compare_f64(d, ref, where="pw512")
+    say("pw512 errors", errs, plan.info())
+
+
+def test_f64_padded_strides_direct():
+    """Non-default strides (padded columns and planes) run the direct variant."""
+    nx, ny, nz = 6, 5, 10
+    p = inputs.make_problem(nx, ny, nz, seed=77)
+    sy, sx = nz + 6, (ny + 2) * (nz + 6) + 10
+    buf = [torch.full((nx + 2) * sx, 3.0e300, dtype=torch.float64) for _ in range(6)]
+
+    def view(t):
+        return t.as_strided((nx + 2, ny + 2, nz), (sx, sy, 1))
+
+    for t, a in zip(buf[:3], (p.u, p.v, p.w)):
+        view(t).copy_(torch.from_numpy(a))
+    dbuf = [t.to(DEV) for t in buf]
+    ins = [view(t) for t in dbuf[:3]]
+    outs = [view(t) for t in dbuf[3:]]
+    c = p.coeffs
+    tz = [torch.from_numpy(x).to(DEV) for x in c.arrays()]
+    plan = B.Plan(B.F64, [B.shape_of(ins[0])], {})
+    assert plan.info()["variant"] == B.VARIANT_DIRECT
+    B.advect(plan, *ins, *outs, c.tcx, c.tcy, *tz)
+    torch.cuda.synchronize()
+    ref = oracle.advect_problem(p)
+    for o, r in zip(outs, ref):
+        g = o.cpu().numpy()
+        assert np.max(np.abs(g[1:-1, 1:-1] - r[1:-1, 1:-1])) <= 1e-12 * np.max(np.abs(r))
+    # padding between columns and planes is never written
+    for t in dbuf[3:]:
+        h = t.cpu().numpy()
+        mask = np.ones_like(h, dtype=bool)
+        idx = np.arange(nz)[None, None, :] + np.arange(1, ny + 1)[None, :, None] * sy + \
+            np.arange(1, nx + 1)[:, None, None] * sx
+        mask[idx.ravel()] = False
+        assert np.all(h[mask] == 3.0e300)
+
+
+def test_variants_agree_to_rounding():
+    p = inputs.make_problem(40, 33, 64, seed=5)
+    outs = []
+    for tuning in TUNINGS:
+        d, _ = _run(p, tuning)
+        outs.append([o.cpu().numpy() for o in d.outputs])
+    for other in outs[1:]:
+        for a, b in zip(outs[0], other):
+            assert np.max(np.abs(a - b)) <= 1e-14 * np.max(np.abs(a))
+
+
+def test_repeat_is_deterministic():
+    p = inputs.make_problem(30, 20, 64, seed=6)
+    d, plan = _run(p, {})
+    first = [o.clone() for o in d.outputs]
+    for _ in range(3):
+        d.run(plan)
+    torch.cuda.synchronize()
+    for a, b in zip(first, d.outputs):
+        assert torch.equal(a, b)
