@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--skip-variants", action="store_true", help="FP64 only")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0: all usable cores, max 16)")
+    ap.add_argument("--copy-probe", type=float, default=0.0,
+                    help="only time a plain device copy of this many GB per direction (HBM calibration)")
     return ap.parse_args()
 
 
@@ -58,6 +60,19 @@ def time_steps(fn, steps, warmup, stream):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def copy_ceiling(gbytes, steps, warmup, dev, stream):
+    """Read+write bandwidth of a plain device-to-device copy (torch's copy kernel)."""
+    import torch
+    n = int(gbytes * 1e9) // 8
+    a = torch.empty(n, dtype=torch.float64, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    ms = time_steps(lambda: b.copy_(a), steps, warmup, stream)
+    moved = 2 * n * 8
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": moved, "ms": round(ms, 5), "gbs": round(moved / (ms * 1e-3) / 1e9, 1)}
 
 
 def cpu_baseline(p, threads):
@@ -114,6 +129,10 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     tuning = json.loads(args.tuning) if args.tuning else None
+    if args.copy_probe > 0:
+        rec = copy_ceiling(args.copy_probe, args.steps, args.warmup, dev, stream)
+        print(json.dumps({"copy_probe": rec}), flush=True)
+        return
 
     t0 = time.perf_counter()
     p = inputs.workload(args.workload)
@@ -149,6 +168,11 @@ def main():
                      "algorithmic_bytes_per_launch": abytes},
         "paper_equivalent_gflops": round(metrics.paper_equivalent_gflops(gpts * 1e9, nz), 1),
     }
+
+    ceiling = copy_ceiling(2.0, 10, 3, dev, stream)
+    result["roofline"]["copy_ceiling_gbs"] = ceiling["gbs"]
+    result["roofline"]["frac_of_copy_ceiling"] = round(achieved / ceiling["gbs"], 4)
+    log("copy ceiling", ceiling)
 
     # ---------------- CPU oracle baseline ----------------
     ref = None

@@ -72,7 +72,7 @@ def test_f64_padded_strides_direct():
     nx, ny, nz = 6, 5, 10
     p = inputs.make_problem(nx, ny, nz, seed=77)
     sy, sx = nz + 6, (ny + 2) * (nz + 6) + 10
-    buf = [torch.full((nx + 2) * sx, 3.0e300, dtype=torch.float64) for _ in range(6)]
+    buf = [torch.full(((nx + 2) * sx,), 3.0e300, dtype=torch.float64) for _ in range(6)]
 
     def view(t):
         return t.as_strided((nx + 2, ny + 2, nz), (sx, sy, 1))
