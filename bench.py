@@ -75,6 +75,22 @@ def copy_ceiling(gbytes, steps, warmup, dev, stream):
     return {"bytes_per_copy": moved, "ms": round(ms, 5), "gbs": round(moved / (ms * 1e-3) / 1e9, 1)}
 
 
+def measured_traffic(kernel_key, chunk, seg):
+    """Calibrated HBM bytes per launch from the committed rocprofv3 counter summary,
+    or None if the kernel sources or launch shape changed since it was taken."""
+    from paper_2107_13500_amd import kernel_sources_sha256
+    path = os.path.join(ROOT, "profiles", kernel_key + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_sha256") != kernel_sources_sha256():
+        return None
+    if rec.get("chunk") != chunk or rec.get("seg") != seg:
+        return None
+    return rec.get("traffic_bytes")
+
+
 def cpu_baseline(p, threads):
     """The FP64 oracle on the same grid, timed on the host; returns (record, reference outputs)."""
     import oracle
@@ -168,6 +184,10 @@ def main():
                      "algorithmic_bytes_per_launch": abytes},
         "paper_equivalent_gflops": round(metrics.paper_equivalent_gflops(gpts * 1e9, nz), 1),
     }
+
+    if info["variant"] == B.VARIANT_MARCH:
+        t = measured_traffic("pw_march_f64_%s" % args.workload, info["chunk"], info["seg"])
+        result["roofline"]["traffic"] = None if t is None else int(round(t))
 
     ceiling = copy_ceiling(2.0, 10, 3, dev, stream)
     result["roofline"]["copy_ceiling_gbs"] = ceiling["gbs"]

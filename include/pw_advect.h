@@ -228,6 +228,16 @@ int32_t pw_perturb_batched(const pw_plan *plan, int32_t ndomains,
    word from the device).  `count` is a host out-pointer. */
 int32_t pw_plan_error_count(const pw_plan *plan, unsigned long long *count);
 
+/* Measurement utility (no part of the stencil): streaming copy src[s] ->
+   dst[s] for s < nstreams (1..3) of `bytes` bytes each (a multiple of 16),
+   with the stencil kernels' access width (16-byte loads, non-temporal 16-byte
+   stores).  Its time gives the attainable HBM read+write bandwidth and its
+   profiler counters calibrate the byte counters.  src, dst: host arrays of
+   device pointers (16-byte aligned, not overlapping); workgroups: grid size
+   (0 = 16 per compute unit of a 256-CU part).  Asynchronous on `stream`. */
+int32_t pw_probe_copy(const void *const *src, void *const *dst, int32_t nstreams,
+                      int64_t bytes, int32_t workgroups, void *stream);
+
 /* Human-readable name of a status code (static string). */
 const char *pw_status_string(int32_t status);
 

@@ -66,6 +66,7 @@ SIGNATURES = {
     "pw_fill_halo_batched": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "pw_perturb_batched": (c_int32, [c_void_p, c_int32, c_void_p, c_uint64, c_void_p, c_double, c_void_p]),
     "pw_plan_error_count": (c_int32, [c_void_p, POINTER(c_ulonglong)]),
+    "pw_probe_copy": (c_int32, [POINTER(c_void_p), POINTER(c_void_p), c_int32, c_int64, c_int32, c_void_p]),
     "pw_status_string": (ctypes.c_char_p, [c_int32]),
     "pw_last_hip_error": (c_int32, []),
 }
@@ -229,6 +230,14 @@ def perturb_batched(plan: Plan, d_args, seed: int, d_call, amplitude: float, str
     check(lib().pw_perturb_batched(plan.handle, plan.ndomains, d_args.data_ptr(), int(seed),
                                    d_call.data_ptr(), float(amplitude), stream_handle(stream)),
           "pw_perturb_batched")
+
+
+def probe_copy(srcs, dsts, nbytes: int, workgroups: int = 0, stream=None) -> None:
+    """pw_probe_copy over lists of device tensors (HBM calibration)."""
+    n = len(srcs)
+    sp = (c_void_p * n)(*[t.data_ptr() for t in srcs])
+    dp = (c_void_p * n)(*[t.data_ptr() for t in dsts])
+    check(lib().pw_probe_copy(sp, dp, n, int(nbytes), int(workgroups), stream_handle(stream)), "pw_probe_copy")
 
 
 def domain_args_tensor(records: Sequence[PwDomainArgs], device):
