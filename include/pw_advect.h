@@ -228,6 +228,34 @@ int32_t pw_perturb_batched(const pw_plan *plan, int32_t ndomains,
    word from the device).  `count` is a host out-pointer. */
 int32_t pw_plan_error_count(const pw_plan *plan, unsigned long long *count);
 
+/* Launch-shape autotuner (the batched form's tile shapes: chunk, segment
+   length, workgroups per CU; the single-domain variant, chunk and segment).
+   Times each candidate tuning on the caller's buffers -- pw_advect with
+   h_args[0] when ndomains == 1, pw_advect_batched with d_args otherwise --
+   as the median of `reps` calls after one warm-up, and returns the fastest.
+     storage, shapes, ndomains  as for pw_advect_plan.
+     h_args      host array (ndomains == 1: one record whose pointers are
+                 device pointers; its shape field is ignored).
+     d_args      device array of ndomains records (ndomains > 1).
+     candidates  host array of ncandidates tunings, or NULL with
+                 ncandidates == 0 for the built-in search space (see
+                 pw_autotune_candidates).
+     best        host out-pointer: fastest tuning.
+     best_ms     host out-pointer or NULL: its median time in ms.
+     all_ms      host array of one float per candidate or NULL: median
+                 times, -1 for candidates the shape cannot use.
+   Overwrites the outputs.  Allocates, creates a stream and synchronises:
+   not for use during stream capture (PW_ERR_CAPTURE).  Returns
+   PW_ERR_UNSUPPORTED if no candidate is usable. */
+int32_t pw_autotune(int32_t storage, const pw_shape *shapes, int32_t ndomains,
+                    const pw_domain_args *h_args, const pw_domain_args *d_args,
+                    const pw_tuning *candidates, int32_t ncandidates, int32_t reps,
+                    pw_tuning *best, float *best_ms, float *all_ms);
+
+/* The built-in autotuner search space: writes up to `capacity` tunings to
+   `out` (host, may be NULL) and returns how many there are. */
+int32_t pw_autotune_candidates(int32_t batched, pw_tuning *out, int32_t capacity);
+
 /* Measurement utility (no part of the stencil): streaming copy src[s] ->
    dst[s] for s < nstreams (1..3) of `bytes` bytes each (a multiple of 16),
    with the stencil kernels' access width (16-byte loads, non-temporal 16-byte

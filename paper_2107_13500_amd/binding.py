@@ -66,6 +66,9 @@ SIGNATURES = {
     "pw_fill_halo_batched": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "pw_perturb_batched": (c_int32, [c_void_p, c_int32, c_void_p, c_uint64, c_void_p, c_double, c_void_p]),
     "pw_plan_error_count": (c_int32, [c_void_p, POINTER(c_ulonglong)]),
+    "pw_autotune": (c_int32, [c_int32, POINTER(PwShape), c_int32, c_void_p, c_void_p, POINTER(PwTuning),
+                              c_int32, c_int32, POINTER(PwTuning), POINTER(c_float), POINTER(c_float)]),
+    "pw_autotune_candidates": (c_int32, [c_int32, POINTER(PwTuning), c_int32]),
     "pw_probe_copy": (c_int32, [POINTER(c_void_p), POINTER(c_void_p), c_int32, c_int64, c_int32, c_void_p]),
     "pw_status_string": (ctypes.c_char_p, [c_int32]),
     "pw_last_hip_error": (c_int32, []),

@@ -1,5 +1,4 @@
-// Storage types, conversions and the compensated product difference used by
-// the PW advection kernels (gfx950).
+// Storage types and conversions used by the PW advection kernels (gfx950).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -46,24 +45,6 @@ template <> __device__ __forceinline__ bf16_t from_compute<bf16_t>(float x) {
         r.bits = static_cast<uint16_t>(u >> 16);
     }
     return r;
-}
-
-// ---------------------------------------------------------------------------
-// a*b - c*d
-// ---------------------------------------------------------------------------
-// FP64: plain expression (the compiler may fuse; parity is judged by norm).
-__device__ __forceinline__ double pdiff(double a, double b, double c, double d) {
-    return a * b - c * d;
-}
-
-// FP32: Kahan's algorithm with fused multiply-adds (Jeannerod, Louvet and
-// Muller, Math. Comp. 82 (2013), error <= 2 ulp of the exact result):
-// w = RN(c d); e = c d - w exactly; f = RN(a b - w); result RN(f - e).
-__device__ __forceinline__ float pdiff(float a, float b, float c, float d) {
-    float w = c * d;
-    float e = __builtin_fmaf(c, d, -w);
-    float f = __builtin_fmaf(a, b, -w);
-    return f - e;
 }
 
 }  // namespace pw

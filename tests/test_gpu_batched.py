@@ -1,0 +1,217 @@
+"""Batched subdomains, halo fill, perturbation, graph replay and autotuner (GPU).
+
+Each domain of a batched call must equal the oracle to 1e-12 (FP64) and be
+bit-identical to a single-domain pw_advect with the same chunk and segment
+shape (the batched kernel runs the same per-tile code).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import DEV, F64_TOL, max_rel, say
+from paper_2107_13500_amd import batched as BT
+from paper_2107_13500_amd import binding as B
+from paper_2107_13500_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [(16, 16, 64), (17, 23, 96), (40, 9, 128), (5, 3, 64), (96, 31, 96), (33, 50, 64), (1, 1, 64),
+         (20, 20, 128), (61, 17, 96)]
+
+
+def small_problems(shapes=SMALL, seed=300):
+    out = []
+    for d, (nx, ny, nz) in enumerate(shapes):
+        out.append(inputs.make_problem(nx, ny, nz, seed + d, dx=25.0 + 7 * d, rho0=1.1 + 0.02 * d,
+                                       scale_height=6000.0 + 400 * d))
+    return out
+
+
+def single_outputs(batch, d, tuning):
+    """pw_advect on domain d's device inputs into fresh buffers."""
+    f = batch.fields[d]
+    outs = [torch.zeros_like(f[0]) for _ in range(3)]
+    plan = B.Plan(batch.storage, [batch.records[d].shape], tuning)
+    p = batch.problems[d]
+    B.advect(plan, f[0], f[1], f[2], *outs, p.coeffs.tcx, p.coeffs.tcy, *batch.tz[d],
+             scales=batch.scales[d] if batch.storage in (B.BF16, B.F16) else None)
+    torch.cuda.synchronize()
+    return outs
+
+
+@pytest.mark.parametrize("tuning", [{"chunk": 256, "seg": 8}, {"chunk": 512, "seg": 64},
+                                    {"chunk": 1024, "seg": 16, "wg_per_cu": 2}],
+                         ids=["c256s8", "c512s64", "c1024s16w2"])
+def test_batched_f64_parity_and_bit_identity(tuning):
+    probs = small_problems()
+    batch = BT.DeviceBatch(probs, B.F64, DEV)
+    plan = batch.plan(tuning)
+    say("batched", tuning, plan.info())
+    batch.advect(plan)
+    torch.cuda.synchronize()
+    assert plan.error_count() == 0
+    single_t = dict(tuning, variant=B.VARIANT_MARCH)
+    single_t.pop("wg_per_cu", None)
+    for d, p in enumerate(probs):
+        ref = oracle.advect_problem(p)
+        got = batch.host_outputs(d)
+        for name, g, r in zip(("su", "sv", "sw"), got, ref):
+            e = max_rel(g[1:-1, 1:-1], r[1:-1, 1:-1])
+            assert e <= F64_TOL, "domain %d %s: %.3e" % (d, name, e)
+        for a, b in zip(batch.fields[d][3:], single_outputs(batch, d, single_t)):
+            assert torch.equal(a[1:-1, 1:-1], b[1:-1, 1:-1]), "domain %d differs from pw_advect" % d
+
+
+@pytest.mark.parametrize("storage", [B.F32, B.BF16, B.F16], ids=["f32", "bf16", "f16"])
+def test_batched_reduced_storage_matches_single_calls(storage):
+    probs = small_problems(seed=400)
+    batch = BT.DeviceBatch(probs, storage, DEV)
+    tuning = {"chunk": 512, "seg": 16}
+    plan = batch.plan(tuning)
+    batch.advect(plan)
+    torch.cuda.synchronize()
+    for d in range(len(probs)):
+        for a, b in zip(batch.fields[d][3:], single_outputs(batch, d, dict(tuning, variant=B.VARIANT_MARCH))):
+            assert torch.equal(a[1:-1, 1:-1], b[1:-1, 1:-1])
+
+
+def test_shape_mismatch_is_skipped_and_counted():
+    probs = small_problems(SMALL[:4], seed=500)
+    batch = BT.DeviceBatch(probs, B.F64, DEV)
+    bad = list(batch.records)
+    rec = B.PwDomainArgs.from_buffer_copy(bytes(bad[2]))
+    rec.shape.nx += 1
+    bad[2] = rec
+    d_bad = B.domain_args_tensor(bad, DEV)
+    plan = batch.plan()
+    for o in batch.fields[2][3:]:
+        o.fill_(123.0)
+    B.advect_batched(plan, d_bad)
+    torch.cuda.synchronize()
+    assert plan.error_count() == 1
+    assert all(torch.all(o == 123.0).item() for o in batch.fields[2][3:])
+    ref = oracle.advect_problem(probs[1])
+    got = batch.host_outputs(1)
+    assert max_rel(got[0][1:-1, 1:-1], ref[0][1:-1, 1:-1]) <= F64_TOL
+
+
+def test_fill_halo_matches_periodic_fill():
+    probs = small_problems(seed=600)
+    batch = BT.DeviceBatch(probs, B.F64, DEV)
+    expect = []
+    for d, p in enumerate(probs):
+        exp = []
+        for f in range(3):
+            t = batch.fields[d][f]
+            t[0].fill_(-1.0)
+            t[-1].fill_(-2.0)
+            t[:, 0].fill_(-3.0)
+            t[:, -1].fill_(-4.0)
+            exp.append(inputs.fill_periodic_halo(t.cpu().numpy().copy()))
+        expect.append(exp)
+    plan = batch.plan()
+    batch.fill_halo(plan)
+    torch.cuda.synchronize()
+    for d in range(len(probs)):
+        for f in range(3):
+            assert np.array_equal(batch.fields[d][f].cpu().numpy(), expect[d][f])
+
+
+def test_perturb_is_deterministic_and_interior_only():
+    probs = small_problems(SMALL[:5], seed=700)
+    a = BT.DeviceBatch(probs, B.F64, DEV)
+    b = BT.DeviceBatch(probs, B.F64, DEV)
+    pa, pb = a.plan(), b.plan()
+    before = [[t.clone() for t in a.fields[d][:3]] for d in range(len(probs))]
+    a.perturb(pa, 42, 1e-3)
+    b.perturb(pb, 42, 1e-3)
+    torch.cuda.synchronize()
+    assert int(a.call.item()) == 1
+    for d in range(len(probs)):
+        for f in range(3):
+            assert torch.equal(a.fields[d][f], b.fields[d][f])
+        for f in range(2):
+            delta = (a.fields[d][f] - before[d][f])
+            inner = delta[1:-1, 1:-1]
+            assert torch.all(inner.abs() <= 1e-3).item() and torch.any(inner != 0).item()
+            assert torch.all(delta[0] == 0).item() and torch.all(delta[:, -1] == 0).item()
+        assert torch.equal(a.fields[d][2], before[d][2])
+    snap = [t.clone() for t in a.fields[0][:2]]
+    a.perturb(pa, 42, 1e-3)       # second call: different noise
+    torch.cuda.synchronize()
+    d2 = a.fields[0][0] - snap[0]
+    d1 = snap[0] - before[0][0]
+    assert not torch.equal(d1, d2)
+
+
+def test_graph_replays_match_eager_steps():
+    probs = small_problems(seed=800)
+    ga = BT.DeviceBatch(probs, B.F64, DEV)
+    eb = BT.DeviceBatch(probs, B.F64, DEV)
+    pa, pb = ga.plan({"chunk": 512, "seg": 16}), eb.plan({"chunk": 512, "seg": 16})
+    g = ga.capture_timestep(pa, seed=7, amplitude=1e-3)
+    scratch = torch.randn(256, 256, device=DEV)
+    for r in range(4):
+        g.replay()
+        eb.timestep(pb, seed=7, amplitude=1e-3)
+        scratch = scratch @ scratch.T / 256.0      # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert int(ga.call.item()) == r + 1
+        for d in range(len(probs)):
+            for x, y in zip(ga.fields[d], eb.fields[d]):
+                assert torch.equal(x, y), "replay %d domain %d differs from the eager step" % (r, d)
+    # the outputs after the last replay are the stencil of the final fields
+    for d in (0, 4, len(probs) - 1):
+        u, v, w = ga.host_fields(d)
+        p = probs[d]
+        ref = oracle.advect(u, v, w, p.coeffs.tcx, p.coeffs.tcy, *p.coeffs.arrays())
+        for g_, r_ in zip(ga.host_outputs(d), ref):
+            assert max_rel(g_[1:-1, 1:-1], r_[1:-1, 1:-1]) <= F64_TOL
+
+
+def test_autotune_picks_a_valid_candidate():
+    probs = small_problems(SMALL[:6], seed=900)
+    batch = BT.DeviceBatch(probs, B.F64, DEV)
+    cands = [{"variant": 2, "chunk": 256, "seg": 16}, {"variant": 2, "chunk": 512, "seg": 64, "wg_per_cu": 2},
+             {"variant": 2, "chunk": 1024, "seg": 8}]
+    best, ms, table = BT.autotune(batch, cands, reps=3)
+    say("autotune", best, ms, table)
+    assert ms > 0 and all(t >= 0 for _, t in table)
+    assert any(all(best[k] == c.get(k, 0) for k in ("chunk", "seg")) for c in cands)
+    plan = batch.plan(best)
+    batch.advect(plan)
+    torch.cuda.synchronize()
+    for d, p in enumerate(probs):
+        ref = oracle.advect_problem(p)
+        for g, r in zip(batch.host_outputs(d), ref):
+            assert max_rel(g[1:-1, 1:-1], r[1:-1, 1:-1]) <= F64_TOL
+
+
+def test_autotune_single_domain_default_space():
+    p = inputs.make_problem(64, 48, 64, seed=901)
+    batch = BT.DeviceBatch([p], B.F64, DEV)
+    best, ms, table = BT.autotune(batch, None, reps=2)
+    say("single-domain autotune", best, ms, len(table))
+    assert ms > 0
+    assert sum(1 for _, t in table if t > 0) >= 3
+
+
+def test_full_384_domain_batch_graph():
+    """The 384-subdomain configuration: graph-captured timestep replayed, sampled domains vs oracle."""
+    specs = inputs.batched_specs()
+    probs = [inputs.make_domain(s) for s in specs]
+    batch = BT.DeviceBatch(probs, B.F64, DEV)
+    plan = batch.plan()
+    say("384 domains", batch.npoints, plan.info())
+    g = batch.capture_timestep(plan, seed=11, amplitude=1e-3)
+    for _ in range(3):
+        g.replay()
+    torch.cuda.synchronize()
+    assert plan.error_count() == 0
+    for d in (0, 1, 77, 191, 300, 383):
+        u, v, w = batch.host_fields(d)
+        p = probs[d]
+        ref = oracle.advect(u, v, w, p.coeffs.tcx, p.coeffs.tcy, *p.coeffs.arrays())
+        for gg, rr in zip(batch.host_outputs(d), ref):
+            assert max_rel(gg[1:-1, 1:-1], rr[1:-1, 1:-1]) <= F64_TOL
