@@ -62,17 +62,20 @@ def time_steps(fn, steps, warmup, stream):
     return e0.elapsed_time(e1) / steps
 
 
-def copy_ceiling(gbytes, steps, warmup, dev, stream):
-    """Read+write bandwidth of a plain device-to-device copy (torch's copy kernel)."""
+def copy_ceiling(gbytes, steps, warmup, dev, stream, nstreams=1, workgroups=65536):
+    """Read+write bandwidth of the library's plain streaming copy (pw_probe_copy)
+    over `nstreams` buffers of `gbytes` GB each."""
     import torch
-    n = int(gbytes * 1e9) // 8
-    a = torch.empty(n, dtype=torch.float64, device=dev).fill_(1.0)
-    b = torch.empty_like(a)
-    ms = time_steps(lambda: b.copy_(a), steps, warmup, stream)
-    moved = 2 * n * 8
-    del a, b
+    from paper_2107_13500_amd import binding as B
+    n = int(gbytes * 1e9) // 16 * 16
+    src = [torch.ones(n // 8, dtype=torch.float64, device=dev) for _ in range(nstreams)]
+    dst = [torch.empty_like(a) for a in src]
+    ms = time_steps(lambda: B.probe_copy(src, dst, n, workgroups, stream), steps, warmup, stream)
+    moved = 2 * n * nstreams
+    del src, dst
     torch.cuda.empty_cache()
-    return {"bytes_per_copy": moved, "ms": round(ms, 5), "gbs": round(moved / (ms * 1e-3) / 1e9, 1)}
+    return {"streams": nstreams, "bytes_per_copy": moved, "ms": round(ms, 5),
+            "gbs": round(moved / (ms * 1e-3) / 1e9, 1)}
 
 
 def measured_traffic(kernel_key, chunk, seg):
@@ -189,13 +192,46 @@ def main():
         t = measured_traffic("pw_march_f64_%s" % args.workload, info["chunk"], info["seg"])
         result["roofline"]["traffic"] = None if t is None else int(round(t))
 
-    ceiling = copy_ceiling(2.0, 10, 3, dev, stream)
+    ceiling = copy_ceiling(2.0, 10, 3, dev, stream, nstreams=1)
+    ceiling3 = copy_ceiling(2.15, 10, 3, dev, stream, nstreams=3)
     result["roofline"]["copy_ceiling_gbs"] = ceiling["gbs"]
-    result["roofline"]["frac_of_copy_ceiling"] = round(achieved / ceiling["gbs"], 4)
-    log("copy ceiling", ceiling)
+    result["roofline"]["copy_ceiling_3x3_streams_gbs"] = ceiling3["gbs"]
+    result["roofline"]["frac_of_copy_ceiling"] = round(achieved / max(ceiling["gbs"], ceiling3["gbs"]), 4)
+    log("copy ceilings", ceiling, ceiling3)
 
-    # ---------------- CPU oracle baseline ----------------
-    ref = None
+    # ---------------- storage-precision variants (outputs kept for the error check) ----------------
+    kept = {}
+    if not args.skip_variants:
+        variants = {}
+        for storage in (B.F32, B.BF16, B.F16):
+            name = B.DTYPE_NAMES[storage]
+            dt = B.torch_dtype(storage)
+            if storage == B.F16:
+                ins, outs_s = inputs.fp16_input_scales(p), inputs.fp16_output_scales(p)
+            else:
+                ins, outs_s = (1.0, 1.0, 1.0), (1.0, 1.0, 1.0)
+            sc = B.make_scales(ins, outs_s)
+            fu, fv, fw = (torch.from_numpy(a).to(dev).mul_(s).to(dt) for a, s in zip((p.u, p.v, p.w), ins))
+            dd = B.DeviceDomain(fu, fv, fw, c.tcx, c.tcy, *tz, scales=sc)
+            pl = B.Plan(storage, [B.shape_of(fu)], tuning)
+            vms = time_steps(lambda: dd.run(pl, stream), args.steps, args.warmup, stream)
+            vb = metrics.algorithmic_bytes(nx, ny, nz, metrics.ELEM_BYTES[name])
+            rec = {"gpoints_per_s": round(p.npoints / (vms * 1e-3) / 1e9, 3), "ms_per_step": round(vms, 5),
+                   "speedup_vs_f64": round(ms / vms, 3),
+                   "hbm_frac": round(vb / (vms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                   "in_scale": list(ins), "out_scale": list(outs_s)}
+            variants[name] = rec
+            kept[name] = (dd.outputs, outs_s)
+            log(name, rec)
+            del fu, fv, fw, pl
+        result["precision"] = variants
+
+    # ---------------- batched subdomains ----------------
+    batches = {}
+    if not args.skip_batched:
+        result["batched"], batches = batched_leg(dev, stream, gpts, log)
+
+    # ---------------- CPU oracle baseline (the only leg that runs the oracle) ----------------
     if not args.skip_cpu:
         usable = len(os.sched_getaffinity(0))
         threads = args.cpu_threads or min(usable, 16)
@@ -205,48 +241,85 @@ def main():
         torch.cuda.synchronize()
         result["parity_f64"] = errors_vs(ref, d64.outputs, (1.0, 1.0, 1.0), nx, ny)
         log("FP64 parity", result["parity_f64"]["max_rel"])
-    del d64, u, v, w
-    torch.cuda.empty_cache()
-
-    # ---------------- storage-precision variants ----------------
-    if not args.skip_variants:
-        variants = {}
-        for storage in (B.F32, B.BF16, B.F16):
-            name = B.DTYPE_NAMES[storage]
-            dt = B.torch_dtype(storage)
-            if storage == B.F16:
-                ins = tuple(inputs.pow2_scale(float(np.max(np.abs(a)))) for a in (p.u, p.v, p.w))
-                outs_s = inputs.fp16_output_scales(p)
-            else:
-                ins, outs_s = (1.0, 1.0, 1.0), (1.0, 1.0, 1.0)
-            sc = B.make_scales(ins, outs_s)
-            fu, fv, fw = (torch.from_numpy(a).to(dev).mul_(s).to(dt) for a, s in zip((p.u, p.v, p.w), ins))
-            dd = B.DeviceDomain(fu, fv, fw, c.tcx, c.tcy, *tz, scales=sc)
-            pl = B.Plan(storage, [B.shape_of(fu)], tuning)
-            vms = time_steps(lambda: dd.run(pl, stream), args.steps, args.warmup, stream)
-            eb = metrics.ELEM_BYTES[name]
-            vb = metrics.algorithmic_bytes(nx, ny, nz, eb)
-            rec = {"gpoints_per_s": round(p.npoints / (vms * 1e-3) / 1e9, 3), "ms_per_step": round(vms, 5),
-                   "speedup_vs_f64": round(ms / vms, 3),
-                   "hbm_frac": round(vb / (vms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                   "in_scale": list(ins), "out_scale": list(outs_s)}
-            if ref is not None:
-                rec["error_vs_f64_oracle"] = errors_vs(ref, dd.outputs, outs_s, nx, ny)
-            variants[name] = rec
-            log(name, rec)
-            del dd, fu, fv, fw, pl
-            torch.cuda.empty_cache()
-        result["precision"] = variants
-
-    # ---------------- batched subdomains ----------------
-    if not args.skip_batched:
-        try:
-            from paper_2107_13500_amd import batched_bench
-            result["batched"] = batched_bench.run(dev, stream, log)
-        except ImportError:
-            pass
+        for name, (outs, outs_s) in kept.items():
+            result["precision"][name]["error_vs_f64_oracle"] = errors_vs(ref, outs, outs_s, nx, ny)
+            log(name, "error", result["precision"][name]["error_vs_f64_oracle"]["max_rel"])
+        del ref
+        for name, batch in batches.items():
+            result["batched"][name]["max_rel_err_sampled"] = batched_errors(batch, threads)
+            log("batched", name, "error", result["batched"][name]["max_rel_err_sampled"])
 
     print(json.dumps(result), flush=True)
+
+
+def batched_leg(dev, stream, f64_gpts, log, replays=100):
+    """384 uneven subdomains, FP64 and FP32: autotuned persistent launch, one
+    graph-captured timestep (perturb u, v; refill halos; advect) replayed
+    `replays` times, compared with the same timestep as one pw_advect launch
+    per domain."""
+    import torch
+    from paper_2107_13500_amd import batched as BT
+    from paper_2107_13500_amd import binding as B
+    from paper_2107_13500_amd import inputs, metrics, tune
+
+    t0 = time.perf_counter()
+    specs = inputs.batched_specs()
+    probs = [inputs.make_domain(sp) for sp in specs]
+    log("batched inputs: %d domains generated in %.1f s" % (len(probs), time.perf_counter() - t0))
+    out, keep = {}, {}
+    for storage in (B.F64, B.F32):
+        name = B.DTYPE_NAMES[storage]
+        batch = BT.DeviceBatch(probs, storage, dev)
+        npts = batch.npoints
+        tuning, tms, hit = tune.tuning_for(batch, reps=5)
+        plan = batch.plan(tuning)
+        eager_ms = time_steps(lambda: batch.advect(plan, stream), 20, 5, stream)
+        g = batch.capture_timestep(plan, seed=inputs.SEED_BASE, amplitude=1e-3)
+        graph_ms = time_steps(g.replay, replays, 3, stream)
+        # baseline: the same timestep with one pw_advect launch per domain, also as a graph
+        plans = batch.per_domain_plans()
+        gp = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(gp):
+            batch.perturb(plan, inputs.SEED_BASE + 1, 1e-3)
+            batch.fill_halo(plan)
+            batch.advect_per_domain(plans)
+        torch.cuda.synchronize()
+        per_dom_ms = time_steps(gp.replay, 20, 3, stream)
+        ebytes = metrics.ELEM_BYTES[name]
+        abytes = sum(metrics.algorithmic_bytes(pp.nx, pp.ny, pp.nz, ebytes) for pp in probs)
+        rec = {"domains": len(probs), "points": npts, "tuning": tuning, "tuning_from_cache": hit,
+               "advect_ms": round(eager_ms, 5),
+               "gpoints_per_s": round(npts / (eager_ms * 1e-3) / 1e9, 3),
+               "hbm_frac": round(abytes / (eager_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "graph_timestep_ms": round(graph_ms, 5), "graph_replays": replays,
+               "per_domain_launch_timestep_ms": round(per_dom_ms, 5),
+               "speedup_vs_per_domain_launches": round(per_dom_ms / graph_ms, 3),
+               "speedup_vs_plain_f64_rate": round(npts / (eager_ms * 1e-3) / 1e9 / f64_gpts, 3),
+               "plan": plan.info()}
+        log("batched", name, rec)
+        out[name] = rec
+        keep[name] = batch
+        del g, gp, plans
+    return out, keep
+
+
+def batched_errors(batch, threads, sample=(0, 1, 2, 57, 128, 191, 255, 300, 350, 383)):
+    """Max-norm relative error of sampled domains' outputs against the oracle on
+    the domains' final (perturbed) fields."""
+    import numpy as np
+    import oracle
+    worst = 0.0
+    for d in sample:
+        if d >= len(batch.problems):
+            continue
+        u, v, w = batch.host_fields(d)
+        p = batch.problems[d]
+        ref = oracle.advect(u, v, w, p.coeffs.tcx, p.coeffs.tcy, *p.coeffs.arrays(), threads=threads)
+        for g, r in zip(batch.host_outputs(d), ref):
+            gi, ri = g[1:-1, 1:-1], r[1:-1, 1:-1]
+            worst = max(worst, float(np.max(np.abs(gi - ri)) / np.max(np.abs(ri))))
+    return worst
 
 
 if __name__ == "__main__":
