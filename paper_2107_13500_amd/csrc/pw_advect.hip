@@ -61,9 +61,11 @@ bool march_possible(const pw_shape& s) {
 }
 
 int32_t auto_seg(const pw_shape& s, int32_t nchunks) {
-    // enough workgroups to fill 256 CUs several times over, but segments long
-    // enough that re-reading the two boundary planes stays a few percent
-    const int64_t target = 4096;
+    // enough workgroups to fill 256 CUs many times over (about 32 per CU), but
+    // segments long enough that re-reading the two boundary planes stays a few
+    // percent (measured on 2048 x 2048 x 64: 64 planes beat 128 for FP32
+    // compute and tie for FP64)
+    const int64_t target = 8192;
     int64_t seg = (int64_t)s.nx * nchunks / target;
     seg = std::max<int64_t>(seg, 16);
     seg = std::min<int64_t>(seg, 256);
@@ -111,9 +113,9 @@ int32_t resolve_launch(int32_t storage, const pw_shape& s, const pw_tuning& t, L
 // ---------------------------------------------------------------------------
 // launches
 // ---------------------------------------------------------------------------
-template <typename ST, int P, bool VEC>
+template <typename ST, int P, bool VEC, int NZ>
 hipError_t launch_march(const DomainArgs& d, const Launch& L, hipStream_t stream) {
-    auto kern = pw_march_kernel<ST, 256, P, VEC>;
+    auto kern = pw_march_kernel<ST, 256, P, VEC, NZ>;
     static std::once_flag once;
     static hipError_t attr_err = hipSuccess;
     std::call_once(once, [&] {
@@ -126,12 +128,14 @@ hipError_t launch_march(const DomainArgs& d, const Launch& L, hipStream_t stream
     return hipGetLastError();
 }
 
-template <typename ST, bool VEC>
+// Column heights 64 (the paper's and MONC's default), 96 and 128 get kernels
+// with the height compiled in; other heights use the general one.
+template <typename ST, bool VEC, int NZ>
 hipError_t dispatch_march_p(const DomainArgs& d, const Launch& L, hipStream_t stream) {
     switch (L.chunk) {
-        case 256: return launch_march<ST, 256, VEC>(d, L, stream);
-        case 512: return launch_march<ST, 512, VEC>(d, L, stream);
-        case 1024: return launch_march<ST, 1024, VEC>(d, L, stream);
+        case 256: return launch_march<ST, 256, VEC, NZ>(d, L, stream);
+        case 512: return launch_march<ST, 512, VEC, NZ>(d, L, stream);
+        case 1024: return launch_march<ST, 1024, VEC, NZ>(d, L, stream);
         default: return hipErrorInvalidValue;
     }
 }
@@ -152,7 +156,15 @@ hipError_t launch_direct(const DomainArgs& d, const Launch& L, hipStream_t strea
 template <typename ST>
 hipError_t launch_typed(const DomainArgs& d, const Launch& L, bool vec, hipStream_t stream) {
     if (L.variant == PW_VARIANT_MARCH) {
-        return vec ? dispatch_march_p<ST, true>(d, L, stream) : dispatch_march_p<ST, false>(d, L, stream);
+        if (vec) {
+            switch (d.nz) {
+                case 64: return dispatch_march_p<ST, true, 64>(d, L, stream);
+                case 96: return dispatch_march_p<ST, true, 96>(d, L, stream);
+                case 128: return dispatch_march_p<ST, true, 128>(d, L, stream);
+                default: return dispatch_march_p<ST, true, 0>(d, L, stream);
+            }
+        }
+        return dispatch_march_p<ST, false, 0>(d, L, stream);
     }
     return launch_direct<ST>(d, L, stream);
 }
@@ -328,12 +340,8 @@ int32_t fill_domain_args(int32_t storage, const pw_shape& s, const void* u, cons
     d.tzc2 = tzc2;
     d.tzd1 = tzd1;
     d.tzd2 = tzd2;
-    d.tcx = tcx;
-    d.tcy = tcy;
-    for (int f = 0; f < 3; ++f) {
-        d.in_inv[f] = 1.0f;
-        d.out_scale[f] = 1.0f;
-    }
+    float in_s[3] = {1.0f, 1.0f, 1.0f};
+    float out_s[3] = {1.0f, 1.0f, 1.0f};
     if (scales && (storage == PW_BF16 || storage == PW_F16)) {
         for (int f = 0; f < 3; ++f) {
             const float a = scales->in_scale[f];
@@ -341,10 +349,11 @@ int32_t fill_domain_args(int32_t storage, const pw_shape& s, const void* u, cons
             if (!(a > 0.0f) || !std::isfinite(a) || !(b > 0.0f) || !std::isfinite(b)) return PW_ERR_INVALID_ARG;
             int ea, eb;
             if (std::frexp(a, &ea) != 0.5f || std::frexp(b, &eb) != 0.5f) return PW_ERR_INVALID_ARG;
-            d.in_inv[f] = 1.0f / a;
-            d.out_scale[f] = b;
+            in_s[f] = a;
+            out_s[f] = b;
         }
     }
+    fold_coefficients(tcx, tcy, in_s, out_s, d.cx, d.cy, d.cz);
     d.nx = s.nx;
     d.ny = s.ny;
     d.nz = s.nz;

@@ -27,7 +27,6 @@ __device__ __forceinline__ bool shape_matches(const pw_shape& a, const BatchDoma
     return a.nx == b.nx && a.ny == b.ny && a.nz == b.nz && a.reserved == 0 && sy == b.sy && sx == b.sx;
 }
 
-__device__ __forceinline__ float inv_or_one(float s) { return s > 0.0f ? 1.0f / s : 1.0f; }
 __device__ __forceinline__ float scale_or_one(float s) { return s > 0.0f ? s : 1.0f; }
 
 template <typename ST>
@@ -43,12 +42,12 @@ __device__ __forceinline__ DomainArgs domain_from(const pw_domain_args& a, const
     d.tzc2 = a.tzc2;
     d.tzd1 = a.tzd1;
     d.tzd2 = a.tzd2;
-    d.tcx = a.tcx;
-    d.tcy = a.tcy;
+    float in_s[3], out_s[3];
     for (int f = 0; f < 3; ++f) {
-        d.in_inv[f] = is16<ST>::value ? inv_or_one(a.scales.in_scale[f]) : 1.0f;
-        d.out_scale[f] = is16<ST>::value ? scale_or_one(a.scales.out_scale[f]) : 1.0f;
+        in_s[f] = is16<ST>::value ? scale_or_one(a.scales.in_scale[f]) : 1.0f;
+        out_s[f] = is16<ST>::value ? scale_or_one(a.scales.out_scale[f]) : 1.0f;
     }
+    fold_coefficients(a.tcx, a.tcy, in_s, out_s, d.cx, d.cy, d.cz);
     d.nx = b.nx;
     d.ny = b.ny;
     d.nz = b.nz;
@@ -72,7 +71,7 @@ __device__ __forceinline__ bool aligned16(const void* p) { return (reinterpret_c
 template <typename ST, int NT, int P>
 __global__ __launch_bounds__(NT) void pw_batched_kernel(const BatchDomain* __restrict__ table, int ndom,
                                                         int64_t ntiles, const pw_domain_args* __restrict__ args,
-                                                        int seg, int wpad, unsigned long long* errors,
+                                                        int seg, unsigned long long* errors,
                                                         int vec_shapes) {
     using CT = typename compute_of<ST>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -93,8 +92,12 @@ __global__ __launch_bounds__(NT) void pw_batched_kernel(const BatchDomain* __res
         const int i_end = min(i_begin + seg - 1, b.nx);
         const bool vec = vec_shapes && aligned16(a.u) && aligned16(a.v) && aligned16(a.w) && aligned16(a.su) &&
                          aligned16(a.sv) && aligned16(a.sw);
-        if (vec) march_tile<ST, NT, P, true>(d, c, i_begin, i_end, wpad, lds);
-        else march_tile<ST, NT, P, false>(d, c, i_begin, i_end, wpad, lds);
+        const int wpad = round_up4(P + 2 * b.nz);
+        if (vec && b.nz == 64) march_tile<ST, NT, P, true, 64>(d, c, i_begin, i_end, wpad, lds);
+        else if (vec && b.nz == 96) march_tile<ST, NT, P, true, 96>(d, c, i_begin, i_end, wpad, lds);
+        else if (vec && b.nz == 128) march_tile<ST, NT, P, true, 128>(d, c, i_begin, i_end, wpad, lds);
+        else if (vec) march_tile<ST, NT, P, true, 0>(d, c, i_begin, i_end, wpad, lds);
+        else march_tile<ST, NT, P, false, 0>(d, c, i_begin, i_end, wpad, lds);
     }
 }
 
@@ -193,9 +196,40 @@ hipError_t launch_batched(const pw_plan* p, const pw_domain_args* args, hipStrea
     });
     if (attr_err != hipSuccess) return attr_err;
     hipLaunchKernelGGL(kern, dim3((unsigned)B.launch.workgroups), dim3(256), (size_t)B.launch.lds_bytes, stream,
-                       B.d_table, p->ndomains, B.launch.tiles, args, B.launch.seg, B.launch.wpad, B.d_errors,
+                       B.d_table, p->ndomains, B.launch.tiles, args, B.launch.seg, B.d_errors,
                        B.vec_shapes ? 1 : 0);
     return hipGetLastError();
+}
+
+template <typename ST, int P>
+int occupancy_of(int64_t lds_bytes) {
+    int n = 0;
+    auto kern = pw_batched_kernel<ST, 256, P>;
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, 256, (size_t)lds_bytes) != hipSuccess) return 0;
+    return n;
+}
+
+template <typename ST>
+int occupancy_typed(int32_t chunk, int64_t lds_bytes) {
+    switch (chunk) {
+        case 256: return occupancy_of<ST, 256>(lds_bytes);
+        case 512: return occupancy_of<ST, 512>(lds_bytes);
+        case 1024: return occupancy_of<ST, 1024>(lds_bytes);
+        default: return 0;
+    }
+}
+
+// Resident workgroups per CU of the batched kernel (registers and LDS).
+int batched_occupancy(int32_t storage, int32_t chunk, int64_t lds_bytes) {
+    switch (storage) {
+        case PW_F64: return occupancy_typed<double>(chunk, lds_bytes);
+        case PW_F32: return occupancy_typed<float>(chunk, lds_bytes);
+        case PW_BF16: return occupancy_typed<bf16_t>(chunk, lds_bytes);
+        case PW_F16: return occupancy_typed<f16_t>(chunk, lds_bytes);
+        default: return 0;
+    }
 }
 
 template <typename ST>
@@ -278,6 +312,8 @@ int32_t batched_plan_init(pw_plan* p) {
     if (e != hipSuccess) return report_hip(e);
     const int64_t by_lds = std::max<int64_t>(1, (160 * 1024) / std::max<int64_t>(L.lds_bytes, 1));
     int64_t per_cu = std::min<int64_t>(by_lds, 8);
+    const int occ = batched_occupancy(p->storage, chunk, L.lds_bytes);
+    if (occ > 0) per_cu = std::min<int64_t>(per_cu, occ);
     if (t.wg_per_cu > 0) per_cu = std::min<int64_t>(per_cu, t.wg_per_cu);
     L.workgroups = std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)prop.multiProcessorCount * per_cu));
     L.nchunks = 0;

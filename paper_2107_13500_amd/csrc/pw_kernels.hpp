@@ -11,6 +11,10 @@
 //         plus one column of y halo on each side -- into registers while the
 //         current plane is computed, so every input element crosses HBM about
 //         once and the loads of plane i+2 overlap the arithmetic of plane i.
+//         With a compile-time column height every LDS offset is an immediate,
+//         the ring rotation is unrolled so the slots are compile-time too, and
+//         each thread computes two consecutive levels, sharing their neighbour
+//         reads and storing both results with one vector store.
 #pragma once
 
 #include <type_traits>
@@ -34,9 +38,10 @@ struct DomainArgs {
     const double* tzc2;
     const double* tzd1;
     const double* tzd2;
-    double tcx, tcy;
-    float in_inv[3];     // 1 / in_scale (16-bit storage only)
-    float out_scale[3];  // out_scale (16-bit storage only)
+    // Per output (su, sv, sw): x and y coefficients and the factor applied to
+    // the per-level vertical coefficients, with the 16-bit storage scales
+    // folded in (all exact powers of two); plain tcx, tcy, 1 otherwise.
+    double cx[3], cy[3], cz[3];
     int32_t nx, ny, nz;
     int32_t pad_;
     int64_t sy, sx;
@@ -54,16 +59,22 @@ template <typename ST> struct is16 { static constexpr bool value = false; };
 template <> struct is16<bf16_t> { static constexpr bool value = true; };
 template <> struct is16<f16_t> { static constexpr bool value = true; };
 
-template <typename ST>
-__device__ __forceinline__ typename compute_of<ST>::type load_in(const ST* p, float inv) {
-    auto x = to_compute(*p);
-    if constexpr (is16<ST>::value) x *= inv;
-    return x;
+// Folded coefficients (see DomainArgs) from tcx, tcy and the storage scales.
+__host__ __device__ inline void fold_coefficients(double tcx, double tcy, const float in_scale[3],
+                                                  const float out_scale[3], double cx[3], double cy[3],
+                                                  double cz[3]) {
+    const double su = in_scale[0], sv = in_scale[1], sw = in_scale[2];
+    const double o[3] = {out_scale[0], out_scale[1], out_scale[2]};
+    const double own[3] = {su, sv, sw};
+    for (int f = 0; f < 3; ++f) {
+        cx[f] = tcx * o[f] / (own[f] * su);
+        cy[f] = tcy * o[f] / (own[f] * sv);
+        cz[f] = o[f] / (own[f] * sw);
+    }
 }
 
 template <typename ST>
-__device__ __forceinline__ void store_out(ST* p, typename compute_of<ST>::type x, float scale) {
-    if constexpr (is16<ST>::value) x *= scale;
+__device__ __forceinline__ void store_out(ST* p, typename compute_of<ST>::type x) {
     ST y = from_compute<ST>(x);
     if constexpr (sizeof(ST) == 2) {
         uint16_t bits;
@@ -74,25 +85,56 @@ __device__ __forceinline__ void store_out(ST* p, typename compute_of<ST>::type x
     }
 }
 
+// Two consecutive outputs p[0], p[1] with one store (p aligned to 2 elements).
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 template <typename ST>
-__device__ __forceinline__ LevelCoefs<typename compute_of<ST>::type> level_coefs(const DomainArgs& d, int k) {
-    using CT = typename compute_of<ST>::type;
-    LevelCoefs<CT> z;
-    if (k >= 2) {
-        z.c1 = static_cast<CT>(d.tzc1[k - 1]);
-        z.c2 = static_cast<CT>(d.tzc2[k - 1]);
-        z.d1 = k < d.nz ? static_cast<CT>(d.tzd1[k - 1]) : CT(0);
-        z.d2 = k < d.nz ? static_cast<CT>(d.tzd2[k - 1]) : CT(0);
+__device__ __forceinline__ void store_pair(ST* p, typename compute_of<ST>::type a, typename compute_of<ST>::type b) {
+    if constexpr (std::is_same<ST, double>::value) {
+        __builtin_nontemporal_store(f64x2{a, b}, reinterpret_cast<f64x2*>(p));
+    } else if constexpr (std::is_same<ST, float>::value) {
+        __builtin_nontemporal_store(f32x2{a, b}, reinterpret_cast<f32x2*>(p));
     } else {
-        z.c1 = z.c2 = z.d1 = z.d2 = CT(0);
+        ST ya = from_compute<ST>(a), yb = from_compute<ST>(b);
+        uint16_t ba, bb;
+        __builtin_memcpy(&ba, &ya, 2);
+        __builtin_memcpy(&bb, &yb, 2);
+        __builtin_nontemporal_store(static_cast<uint32_t>(ba) | (static_cast<uint32_t>(bb) << 16),
+                                    reinterpret_cast<uint32_t*>(p));
     }
-    return z;
+}
+
+template <typename ST>
+__device__ __forceinline__ PointCoefs<typename compute_of<ST>::type> point_coefs(const DomainArgs& d, int k) {
+    using CT = typename compute_of<ST>::type;
+    PointCoefs<CT> c;
+    c.xu = static_cast<CT>(d.cx[0]);
+    c.yu = static_cast<CT>(d.cy[0]);
+    c.xv = static_cast<CT>(d.cx[1]);
+    c.yv = static_cast<CT>(d.cy[1]);
+    c.xw = static_cast<CT>(d.cx[2]);
+    c.yw = static_cast<CT>(d.cy[2]);
+    double z1 = 0.0, z2 = 0.0, e1 = 0.0, e2 = 0.0;
+    if (k >= 2) {
+        z1 = d.tzc1[k - 1];
+        z2 = d.tzc2[k - 1];
+        if (k < d.nz) {
+            e1 = d.tzd1[k - 1];
+            e2 = d.tzd2[k - 1];
+        }
+    }
+    c.z1u = static_cast<CT>(z1 * d.cz[0]);
+    c.z2u = static_cast<CT>(z2 * d.cz[0]);
+    c.z1v = static_cast<CT>(z1 * d.cz[1]);
+    c.z2v = static_cast<CT>(z2 * d.cz[1]);
+    c.z1w = static_cast<CT>(e1 * d.cz[2]);
+    c.z2w = static_cast<CT>(e2 * d.cz[2]);
+    return c;
 }
 
 // ---------------------------------------------------------------------------
 // direct variant
 // ---------------------------------------------------------------------------
-// Accessor wrapper with the u<>/v<>/w<> names the stencil expects.
 template <typename ST>
 struct GAcc {
     using CT = typename compute_of<ST>::type;
@@ -100,13 +142,12 @@ struct GAcc {
     const ST* pv;
     const ST* pw;
     int64_t sy, sx;
-    float iu, iv, iw;
     template <int dk, int dj, int di>
-    __device__ __forceinline__ CT u() const { return load_in(pu + (dk + dj * sy + di * sx), iu); }
+    __device__ __forceinline__ CT u() const { return to_compute(pu[dk + dj * sy + di * sx]); }
     template <int dk, int dj, int di>
-    __device__ __forceinline__ CT v() const { return load_in(pv + (dk + dj * sy + di * sx), iv); }
+    __device__ __forceinline__ CT v() const { return to_compute(pv[dk + dj * sy + di * sx]); }
     template <int dk, int dj, int di>
-    __device__ __forceinline__ CT w() const { return load_in(pw + (dk + dj * sy + di * sx), iw); }
+    __device__ __forceinline__ CT w() const { return to_compute(pw[dk + dj * sy + di * sx]); }
 };
 
 // grid: x over the ny*nz points of a plane in blocks of NT, y over x planes.
@@ -120,13 +161,13 @@ __global__ __launch_bounds__(NT) void pw_direct_kernel(DomainArgs d) {
     const int i = blockIdx.y + 1;
     const int64_t off = (int64_t)(k - 1) + (int64_t)j * d.sy + (int64_t)i * d.sx;
     GAcc<ST> A{static_cast<const ST*>(d.u) + off, static_cast<const ST*>(d.v) + off,
-               static_cast<const ST*>(d.w) + off, d.sy, d.sx, d.in_inv[0], d.in_inv[1], d.in_inv[2]};
-    const LevelCoefs<CT> z = level_coefs<ST>(d, k);
+               static_cast<const ST*>(d.w) + off, d.sy, d.sx};
+    const PointCoefs<CT> c = point_coefs<ST>(d, k);
     CT su, sv, sw;
-    pw_point<CT>(A, k, d.nz, static_cast<CT>(d.tcx), static_cast<CT>(d.tcy), z, su, sv, sw);
-    store_out(static_cast<ST*>(d.su) + off, su, d.out_scale[0]);
-    store_out(static_cast<ST*>(d.sv) + off, sv, d.out_scale[1]);
-    store_out(static_cast<ST*>(d.sw) + off, sw, d.out_scale[2]);
+    pw_point<typename arith_of<ST>::type, true>(A, k, d.nz, c, su, sv, sw);
+    store_out(static_cast<ST*>(d.su) + off, su);
+    store_out(static_cast<ST*>(d.sv) + off, sv);
+    store_out(static_cast<ST*>(d.sw) + off, sw);
 }
 
 // ---------------------------------------------------------------------------
@@ -144,156 +185,263 @@ __device__ __forceinline__ int xcd_tile(int b, int G) {
     return x * q + (x < r ? x : r) + slot;
 }
 
-template <typename CT>
+// LDS reads around one point; NZ > 0 makes every offset an immediate.
+template <typename CT, int NZ, int WPAD>
 struct LdsAcc {
-    const CT* m;   // slot of plane i-1, at the point's window index
+    const CT* m;   // plane i-1 at the point's window index
     const CT* c;   // plane i
     const CT* p;   // plane i+1
-    int nz, wp;
+    int nz_rt, wp_rt;
+    __device__ __forceinline__ int nz() const { return NZ > 0 ? NZ : nz_rt; }
+    __device__ __forceinline__ int wp() const { return NZ > 0 ? WPAD : wp_rt; }
     template <int di> __device__ __forceinline__ const CT* sel() const {
         return di < 0 ? m : (di > 0 ? p : c);
     }
     template <int dk, int dj, int di>
-    __device__ __forceinline__ CT u() const { return sel<di>()[dk + dj * nz]; }
+    __device__ __forceinline__ CT u() const { return sel<di>()[dk + dj * nz()]; }
     template <int dk, int dj, int di>
-    __device__ __forceinline__ CT v() const { return sel<di>()[wp + dk + dj * nz]; }
+    __device__ __forceinline__ CT v() const { return sel<di>()[wp() + dk + dj * nz()]; }
     template <int dk, int dj, int di>
-    __device__ __forceinline__ CT w() const { return sel<di>()[2 * wp + dk + dj * nz]; }
+    __device__ __forceinline__ CT w() const { return sel<di>()[2 * wp() + dk + dj * nz()]; }
 };
 
-template <typename ST, int NT, int P, bool VEC>
-struct March {
+constexpr int round_up4(int x) { return (x + 3) / 4 * 4; }
+
+template <typename CT> struct vec2_of;
+template <> struct vec2_of<double> { using type = f64x2; };
+template <> struct vec2_of<float> { using type = f32x2; };
+
+// LDS reads for point O (0 or 1) of a pair of consecutive levels whose first
+// point sits at an even window index: every read is an aligned two-element
+// load (8 or 16 bytes per lane, so lanes at an 8- or 16-byte stride hit the
+// LDS banks without conflicts), and the two points' identical loads are
+// shared.
+template <typename CT, int NZ, int WPAD, int O>
+struct PairAcc {
+    const CT* m;   // plane i-1 at the pair's (even) window index
+    const CT* c;   // plane i
+    const CT* p;   // plane i+1
+    template <int di> __device__ __forceinline__ const CT* sel() const {
+        return di < 0 ? m : (di > 0 ? p : c);
+    }
+    template <int F, int dk, int dj, int di>
+    __device__ __forceinline__ CT get() const {
+        constexpr int e = O + dk;                              // -1 .. 2 from the pair start
+        constexpr int start = e < 0 ? -2 : (e >= 2 ? 2 : 0);   // aligned two-element block
+        using V2 = typename vec2_of<CT>::type;
+        const V2 val = *reinterpret_cast<const V2*>(sel<di>() + F * WPAD + dj * NZ + start);
+        return val[e - start];
+    }
+    template <int dk, int dj, int di> __device__ __forceinline__ CT u() const { return get<0, dk, dj, di>(); }
+    template <int dk, int dj, int di> __device__ __forceinline__ CT v() const { return get<1, dk, dj, di>(); }
+    template <int dk, int dj, int di> __device__ __forceinline__ CT w() const { return get<2, dk, dj, di>(); }
+};
+
+// One (chunk, segment) tile of the march: chunk c of the interior (j, k) run,
+// planes i_begin .. i_end.  Every thread of the workgroup must run it (it
+// holds barriers); `lds` must hold 9 * wpad compute-type elements.
+// NZ > 0: the domain's nz equals NZ and wpad equals round_up4(P + 2 NZ).
+template <typename ST, int NT, int P, bool VEC, int NZ>
+struct MarchTile {
     using CT = typename compute_of<ST>::type;
-    static constexpr int VW = VEC ? int(16 / sizeof(ST)) : 1;           // elements per load
-    static constexpr int WMAX = P + 2 * kMarchMaxNz;                      // largest window
-    static constexpr int NVL = (WMAX + NT * VW - 1) / (NT * VW);         // loads per field per thread
-    static constexpr int PPT = P / NT;                                    // points per thread
+    static constexpr int VW = VEC ? int(16 / sizeof(ST)) : 1;            // elements per load
+    static constexpr int WMAX = P + 2 * (NZ > 0 ? NZ : kMarchMaxNz);      // largest window
+    static constexpr int NVR = (3 * (WMAX / VW) + NT - 1) / NT;           // load rounds per thread (3 fields)
+    static constexpr int PPT = P / NT;                                     // points per thread
+    static constexpr bool PAIR = VEC && NZ > 0 && NZ % 2 == 0 && P % (2 * NT) == 0;
+    static constexpr int WPAD = NZ > 0 ? round_up4(P + 2 * NZ) : 0;
     using Raw = typename std::conditional<VEC, uint4, ST>::type;
     static_assert(P % NT == 0, "P must be a multiple of the block size");
 
-    struct Stage {
-        Raw r[3][NVL];
-    };
+    const DomainArgs& d;
+    CT* lds;
+    int nz_rt, wpad_rt, wb, wlen, pend;
+    int li[PPT];
+    int kk[PPT];
+    bool live[PPT];
+    CT hx[3], hy[3];       // uniform x and y coefficients of su, sv, sw
+    CT zc[PPT][6];         // per-level vertical coefficients of each point
+    // The window vectors of all three fields are spread over the workgroup:
+    // round r of this thread moves vector t + r NT -- field fsel[r] (-1: none),
+    // element offset goff[r] within the plane window, LDS offset loff[r].
+    int fsel[NVR];
+    int goff[NVR];
+    int loff[NVR];
+    Raw st[NVR];
 
-    // Issue the global loads of window [wb, wb + wlen) of plane ip.
-    static __device__ __forceinline__ void load(Stage& st, const DomainArgs& d, int64_t ip, int wb, int wlen) {
-        const ST* f[3] = {static_cast<const ST*>(d.u), static_cast<const ST*>(d.v), static_cast<const ST*>(d.w)};
+    __device__ __forceinline__ int nz() const { return NZ > 0 ? NZ : nz_rt; }
+    __device__ __forceinline__ int wpad() const { return NZ > 0 ? WPAD : wpad_rt; }
+    __device__ __forceinline__ int slot_elems() const { return 3 * wpad(); }
+
+    __device__ __forceinline__ MarchTile(const DomainArgs& dd, int c, int wpad_in, CT* l)
+        : d(dd), lds(l), nz_rt(dd.nz), wpad_rt(wpad_in) {
+        const int n = nz();
+        const int p0 = n + c * P;                       // first point of the chunk (j >= 1)
+        pend = min(p0 + P, (d.ny + 1) * n);             // one past the last interior point
+        wb = p0 - n;                                    // window start: one column of y halo
+        wlen = min(P + 2 * n, (d.ny + 2) * n - wb);
+        const int nvec = wlen / VW;   // vectors per field (wlen is a multiple of VW)
 #pragma unroll
-        for (int fi = 0; fi < 3; ++fi) {
-            const ST* base = f[fi] + ip * d.sx + wb;
+        for (int r = 0; r < NVR; ++r) {
+            const int v = (int)threadIdx.x + r * NT;
+            const int f = v < 3 * nvec ? v / nvec : -1;
+            const int q = (v - (f < 0 ? 0 : f) * nvec) * VW;
+            fsel[r] = f;
+            goff[r] = wb + q;
+            loff[r] = (f < 0 ? 0 : f) * wpad() + q;
+        }
 #pragma unroll
-            for (int r = 0; r < NVL; ++r) {
-                const int q = (r * NT + (int)threadIdx.x) * VW;
-                if (q < wlen) st.r[fi][r] = *reinterpret_cast<const Raw*>(base + q);
+        for (int q = 0; q < PPT; ++q) {
+            const int t = (int)threadIdx.x;
+            const int p = PAIR ? p0 + 2 * (t + NT * (q / 2)) + (q % 2) : p0 + t + NT * q;
+            live[q] = p < pend;
+            kk[q] = p % n + 1;
+            li[q] = p - wb;
+            const PointCoefs<CT> c = point_coefs<ST>(d, live[q] ? kk[q] : 1);
+            zc[q][0] = c.z1u;
+            zc[q][1] = c.z2u;
+            zc[q][2] = c.z1v;
+            zc[q][3] = c.z2v;
+            zc[q][4] = c.z1w;
+            zc[q][5] = c.z2w;
+        }
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            hx[f] = static_cast<CT>(d.cx[f]);
+            hy[f] = static_cast<CT>(d.cy[f]);
+        }
+    }
+
+    // Issue the global loads of the window of plane ip.
+    __device__ __forceinline__ void load(int64_t ip) {
+        const int64_t po = ip * d.sx;
+#pragma unroll
+        for (int r = 0; r < NVR; ++r) {
+            const int f = fsel[r];
+            if (f >= 0) {
+                const ST* base = static_cast<const ST*>(f == 0 ? d.u : (f == 1 ? d.v : d.w));
+                st[r] = *reinterpret_cast<const Raw*>(base + po + goff[r]);
             }
         }
     }
 
-    // Convert staged values to the compute type and write them to an LDS slot.
-    static __device__ __forceinline__ void put(const Stage& st, CT* slot, int wpad, int wlen, const DomainArgs& d) {
+    // Convert the staged values to the compute type and write them to a slot.
+    __device__ __forceinline__ void put(int sidx) {
+        CT* slot = lds + sidx * slot_elems();
 #pragma unroll
-        for (int fi = 0; fi < 3; ++fi) {
+        for (int r = 0; r < NVR; ++r) {
+            if (fsel[r] >= 0) {
+                union {
+                    Raw raw;
+                    ST e[VW];
+                } cv;
+                cv.raw = st[r];
+                CT out[VW];
 #pragma unroll
-            for (int r = 0; r < NVL; ++r) {
-                const int q = (r * NT + (int)threadIdx.x) * VW;
-                if (q < wlen) {
-                    union {
-                        Raw raw;
-                        ST e[VW];
-                    } cv;
-                    cv.raw = st.r[fi][r];
-                    CT out[VW];
+                for (int n = 0; n < VW; ++n) out[n] = to_compute(cv.e[n]);
+                CT* dst = slot + loff[r];
+                if constexpr (VW * sizeof(CT) >= 16) {
 #pragma unroll
-                    for (int n = 0; n < VW; ++n) {
-                        out[n] = to_compute(cv.e[n]);
-                        if constexpr (is16<ST>::value) out[n] *= d.in_inv[fi];
+                    for (int n = 0; n < VW; n += 16 / (int)sizeof(CT)) {
+                        *reinterpret_cast<uint4*>(dst + n) = *reinterpret_cast<const uint4*>(out + n);
                     }
-                    CT* dst = slot + fi * wpad + q;
-                    if constexpr (VW * sizeof(CT) >= 16) {
+                } else {
 #pragma unroll
-                        for (int n = 0; n < VW; n += 16 / (int)sizeof(CT)) {
-                            *reinterpret_cast<uint4*>(dst + n) = *reinterpret_cast<const uint4*>(out + n);
-                        }
-                    } else {
-#pragma unroll
-                        for (int n = 0; n < VW; ++n) dst[n] = out[n];
-                    }
+                    for (int n = 0; n < VW; ++n) dst[n] = out[n];
                 }
             }
         }
     }
+
+    // Compute plane i from the slots sm (plane i-1), sc (plane i), sp (plane i+1).
+    __device__ __forceinline__ void compute(int i, int sm, int sc, int sp) {
+        const int64_t obase = (int64_t)i * d.sx + wb;
+        const int se = slot_elems();
+        using AR = typename arith_of<ST>::type;
+        CT res[PPT][3];
+#pragma unroll
+        for (int q = 0; q < PPT; ++q) {
+            const int l = li[q];
+            const PointCoefs<CT> c{hx[0], hy[0], zc[q][0], zc[q][1], hy[1], hx[1], zc[q][2], zc[q][3],
+                                   hx[2], hy[2], zc[q][4], zc[q][5]};
+            if constexpr (PAIR) {
+                const int l0 = li[q & ~1];   // the pair's first (even) index
+                if (q % 2 == 0) {
+                    PairAcc<CT, NZ, WPAD, 0> A{lds + sm * se + l0, lds + sc * se + l0, lds + sp * se + l0};
+                    pw_point<AR, false>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2]);
+                } else {
+                    PairAcc<CT, NZ, WPAD, 1> A{lds + sm * se + l0, lds + sc * se + l0, lds + sp * se + l0};
+                    pw_point<AR, false>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2]);
+                }
+            } else {
+                LdsAcc<CT, NZ, WPAD> A{lds + sm * se + l, lds + sc * se + l, lds + sp * se + l, nz_rt, wpad()};
+                pw_point<AR, false>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2]);
+            }
+        }
+        ST* outs[3] = {static_cast<ST*>(d.su), static_cast<ST*>(d.sv), static_cast<ST*>(d.sw)};
+        if constexpr (PAIR) {
+#pragma unroll
+            for (int q = 0; q < PPT; q += 2) {
+                if (!live[q]) continue;   // a pair never straddles the chunk end (P, nz even)
+#pragma unroll
+                for (int f = 0; f < 3; ++f) store_pair(outs[f] + obase + li[q], res[q][f], res[q + 1][f]);
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+                if (!live[q]) continue;
+#pragma unroll
+                for (int f = 0; f < 3; ++f) store_out(outs[f] + obase + li[q], res[q][f]);
+            }
+        }
+    }
+
+    // One march step: publish plane i+1, prefetch plane i+2, compute plane i.
+    __device__ __forceinline__ void step(int i, int i_end, int sm, int sc, int sp) {
+        put(sp);
+        __syncthreads();
+        if (i + 2 <= i_end + 1) load((int64_t)(i + 2));
+        compute(i, sm, sc, sp);
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ void run(int i_begin, int i_end) {
+        load((int64_t)(i_begin - 1));
+        put(0);
+        load((int64_t)i_begin);
+        put(1);
+        load((int64_t)(i_begin + 1));
+        if constexpr (NZ > 0) {
+            // ring rotation unrolled: every slot offset is a compile-time constant
+            for (int i = i_begin; i <= i_end; i += 3) {
+                step(i, i_end, 0, 1, 2);
+                if (i + 1 > i_end) break;
+                step(i + 1, i_end, 1, 2, 0);
+                if (i + 2 > i_end) break;
+                step(i + 2, i_end, 2, 0, 1);
+            }
+        } else {
+            int sm = 0, sc = 1, sp = 2;
+            for (int i = i_begin; i <= i_end; ++i) {
+                step(i, i_end, sm, sc, sp);
+                const int t = sm;
+                sm = sc;
+                sc = sp;
+                sp = t;
+            }
+        }
+    }
 };
 
-// One (chunk, segment) tile of the march: chunk c of the interior (j, k) run,
-// planes i_begin .. i_end.  Every thread of the workgroup must call this (it
-// holds barriers); `lds` must hold 9 * wpad compute-type elements.
-template <typename ST, int NT, int P, bool VEC>
+template <typename ST, int NT, int P, bool VEC, int NZ>
 __device__ __forceinline__ void march_tile(const DomainArgs& d, int c, int i_begin, int i_end, int wpad,
                                            typename compute_of<ST>::type* lds) {
-    using M = March<ST, NT, P, VEC>;
-    using CT = typename M::CT;
-
-    const int nz = d.nz;
-    const int p0 = nz + c * P;                        // first point of the chunk (j >= 1)
-    const int pend = min(p0 + P, (d.ny + 1) * nz);    // one past the last interior point
-    const int wb = p0 - nz;                           // window start: one column of y halo
-    const int wlen = min(P + 2 * nz, (d.ny + 2) * nz - wb);
-    const int slot_elems = 3 * wpad;
-
-    // per-point constants: level, coefficients, window index
-    int kk[M::PPT];
-    int li[M::PPT];
-    bool live[M::PPT];
-    LevelCoefs<CT> zc[M::PPT];
-#pragma unroll
-    for (int r = 0; r < M::PPT; ++r) {
-        const int p = p0 + r * NT + (int)threadIdx.x;
-        live[r] = p < pend;
-        kk[r] = p % nz + 1;
-        li[r] = p - wb;
-        zc[r] = level_coefs<ST>(d, live[r] ? kk[r] : 1);
-    }
-    const CT tcx = static_cast<CT>(d.tcx);
-    const CT tcy = static_cast<CT>(d.tcy);
-
-    typename M::Stage st;
-    // prologue: planes i_begin-1 and i_begin straight into their slots, then
-    // plane i_begin+1 into registers
-    int sm = 0, sc = 1, sp = 2;                       // slots of planes i-1, i, i+1
-    M::load(st, d, (int64_t)(i_begin - 1), wb, wlen);
-    M::put(st, lds + sm * slot_elems, wpad, wlen, d);
-    M::load(st, d, (int64_t)i_begin, wb, wlen);
-    M::put(st, lds + sc * slot_elems, wpad, wlen, d);
-    M::load(st, d, (int64_t)(i_begin + 1), wb, wlen);
-
-    for (int i = i_begin; i <= i_end; ++i) {
-        M::put(st, lds + sp * slot_elems, wpad, wlen, d);
-        __syncthreads();
-        if (i + 2 <= i_end + 1) M::load(st, d, (int64_t)(i + 2), wb, wlen);
-
-        const int64_t obase = (int64_t)i * d.sx;
-#pragma unroll
-        for (int r = 0; r < M::PPT; ++r) {
-            if (!live[r]) continue;
-            const int l = li[r];
-            LdsAcc<CT> A{lds + sm * slot_elems + l, lds + sc * slot_elems + l, lds + sp * slot_elems + l, nz, wpad};
-            CT su, sv, sw;
-            pw_point<CT>(A, kk[r], nz, tcx, tcy, zc[r], su, sv, sw);
-            const int64_t o = obase + (wb + l);
-            store_out(static_cast<ST*>(d.su) + o, su, d.out_scale[0]);
-            store_out(static_cast<ST*>(d.sv) + o, sv, d.out_scale[1]);
-            store_out(static_cast<ST*>(d.sw) + o, sw, d.out_scale[2]);
-        }
-        __syncthreads();
-        const int t = sm;
-        sm = sc;
-        sc = sp;
-        sp = t;
-    }
+    MarchTile<ST, NT, P, VEC, NZ> t(d, c, wpad, lds);
+    t.run(i_begin, i_end);
 }
 
 // Single domain: one workgroup per (chunk, segment) tile.
-template <typename ST, int NT, int P, bool VEC>
+template <typename ST, int NT, int P, bool VEC, int NZ>
 __global__ __launch_bounds__(NT) void pw_march_kernel(DomainArgs d, MarchGeom g) {
     using CT = typename compute_of<ST>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -303,7 +451,7 @@ __global__ __launch_bounds__(NT) void pw_march_kernel(DomainArgs d, MarchGeom g)
     const int s = tile / g.nchunks;
     const int i_begin = 1 + s * g.seg;
     const int i_end = min(i_begin + g.seg - 1, d.nx);
-    march_tile<ST, NT, P, VEC>(d, c, i_begin, i_end, g.wpad, lds);
+    march_tile<ST, NT, P, VEC, NZ>(d, c, i_begin, i_end, g.wpad, lds);
 }
 
 }  // namespace pw

@@ -13,13 +13,20 @@
 //   cross  E (v1 + v2) - G (v3 + v4)         advected by another velocity
 //   vert   c1 a (w1 + w2) - c2 c (w3 + w4)   vertical, per-level coefficients
 //   vself  d1 m (w + m) - d2 p (w + p)       w along z
-// FP64 evaluates them exactly as written (Listing 1's order).  FP32 (the
-// reduced-storage forms) evaluates the algebraically identical difference-
-// first forms below: neighbouring values are subtracted first, which is exact
-// when they are within a factor of two of each other (Sterbenz), so the
-// rounding error is relative to the result instead of to the two cancelling
-// products; the coefficient-weighted vertical difference c1 a - c2 c uses
-// Kahan's fused multiply-add algorithm.
+// Three arithmetic policies evaluate them:
+//   ArithF64    FP64, exactly as written (Listing 1's order).
+//   ArithSplit  FP32 storage, FP32 compute: algebraically identical
+//               difference-first forms -- neighbouring values are subtracted
+//               first, which is exact when they are within a factor of two of
+//               each other (Sterbenz), so the rounding error is relative to the
+//               result instead of to the two cancelling products; the
+//               coefficient-weighted vertical difference c1 a - c2 c uses
+//               Kahan's fused multiply-add algorithm.
+//   ArithKahan  16-bit storage, FP32 compute: the sums of two stored values
+//               are exact in FP32, and each product difference E F - G H is
+//               evaluated by Kahan's FMA algorithm (error <= 2 ulp of the
+//               result; Jeannerod, Louvet, Muller, Math. Comp. 82 (2013)); the
+//               self term uses the exact factorisation (A - C)(U + A + C).
 //
 // `A` reads an input at a compile-time offset (dk, dj, di) from the point:
 //   A.template u<dk, dj, di>(), A.template v<...>(), A.template w<...>().
@@ -32,64 +39,111 @@
 namespace pw {
 
 // ---------------------------------------------------------------- FP64: as written
-__device__ __forceinline__ double self_flux(double A, double U, double C) {
-    return A * (U + A) - C * (U + C);
-}
-__device__ __forceinline__ double cross_flux(double E, double v1, double v2, double G, double v3, double v4) {
-    return E * (v1 + v2) - G * (v3 + v4);
-}
-__device__ __forceinline__ double add_vert(double s, double c1, double a, double w1, double w2, double c2, double c,
-                                           double w3, double w4) {
-    return (s + c1 * a * (w1 + w2)) - c2 * c * (w3 + w4);
-}
-__device__ __forceinline__ double add_vself(double s, double d1, double m, double w, double d2, double p) {
-    return (s + d1 * m * (w + m)) - d2 * p * (w + p);
-}
-
-// ---------------------------------------------------------------- FP32: difference first
-// A (U + A) - C (U + C) = (A - C) (U + A + C)
-__device__ __forceinline__ float self_flux(float A, float U, float C) {
-    return (A - C) * ((U + A) + C);
-}
-// E F - G H = ((E - G)(F + H) + (E + G)(F - H)) / 2, with F - H = (v1 - v3) + (v2 - v4)
-__device__ __forceinline__ float cross_flux(float E, float v1, float v2, float G, float v3, float v4) {
-    const float fph = (v1 + v2) + (v3 + v4);
-    const float fmh = (v1 - v3) + (v2 - v4);
-    return 0.5f * __builtin_fmaf(E - G, fph, (E + G) * fmh);
-}
-// c1 a (w1 + w2) - c2 c (w3 + w4) with e - g = c1 a - c2 c by Kahan's algorithm
-__device__ __forceinline__ float add_vert(float s, float c1, float a, float w1, float w2, float c2, float c,
-                                          float w3, float w4) {
-    const float g = c2 * c;
-    const float eg = __builtin_fmaf(c2, c, -g);            // c2 c - g, exact
-    const float emg = __builtin_fmaf(c1, a, -g) - eg;      // c1 a - c2 c
-    const float epg = __builtin_fmaf(c1, a, g);            // c1 a + c2 c
-    const float fph = (w1 + w2) + (w3 + w4);
-    const float fmh = (w1 - w3) + (w2 - w4);
-    return s + 0.5f * __builtin_fmaf(emg, fph, epg * fmh);
-}
-// d1 m (w + m) - d2 p (w + p): F - H = m - p, F + H = (w + m) + (w + p)
-__device__ __forceinline__ float add_vself(float s, float d1, float m, float w, float d2, float p) {
-    const float g = d2 * p;
-    const float eg = __builtin_fmaf(d2, p, -g);
-    const float emg = __builtin_fmaf(d1, m, -g) - eg;
-    const float epg = __builtin_fmaf(d1, m, g);
-    return s + 0.5f * __builtin_fmaf(emg, (w + m) + (w + p), epg * (m - p));
-}
-
-template <typename CT>
-struct LevelCoefs {
-    CT c1, c2, d1, d2;   // tzc1(k), tzc2(k), tzd1(k), tzd2(k)
+struct ArithF64 {
+    using T = double;
+    static __device__ __forceinline__ double self_flux(double A, double U, double C) {
+        return A * (U + A) - C * (U + C);
+    }
+    static __device__ __forceinline__ double cross_flux(double E, double v1, double v2, double G, double v3,
+                                                        double v4) {
+        return E * (v1 + v2) - G * (v3 + v4);
+    }
+    static __device__ __forceinline__ double add_vert(double s, double c1, double a, double w1, double w2, double c2,
+                                                      double c, double w3, double w4) {
+        return (s + c1 * a * (w1 + w2)) - c2 * c * (w3 + w4);
+    }
+    static __device__ __forceinline__ double add_vself(double s, double d1, double m, double w, double d2, double p) {
+        return (s + d1 * m * (w + m)) - d2 * p * (w + p);
+    }
 };
 
-template <typename CT, typename Acc>
-__device__ __forceinline__ void pw_point(const Acc& A, int k, int nz, CT tcx, CT tcy,
-                                         const LevelCoefs<CT>& z, CT& su, CT& sv, CT& sw) {
-    if (k < 2) {
-        su = CT(0);
-        sv = CT(0);
-        sw = CT(0);
-        return;
+// ---------------------------------------------------------------- FP32: difference first
+struct ArithSplit {
+    using T = float;
+    // A (U + A) - C (U + C) = (A - C) (U + A + C)
+    static __device__ __forceinline__ float self_flux(float A, float U, float C) { return (A - C) * ((U + A) + C); }
+    // E F - G H = ((E - G)(F + H) + (E + G)(F - H)) / 2, with F - H = (v1 - v3) + (v2 - v4)
+    static __device__ __forceinline__ float cross_flux(float E, float v1, float v2, float G, float v3, float v4) {
+        const float fph = (v1 + v2) + (v3 + v4);
+        const float fmh = (v1 - v3) + (v2 - v4);
+        return 0.5f * __builtin_fmaf(E - G, fph, (E + G) * fmh);
+    }
+    // c1 a (w1 + w2) - c2 c (w3 + w4) with e - g = c1 a - c2 c by Kahan's algorithm
+    static __device__ __forceinline__ float add_vert(float s, float c1, float a, float w1, float w2, float c2, float c,
+                                                     float w3, float w4) {
+        const float g = c2 * c;
+        const float eg = __builtin_fmaf(c2, c, -g);            // c2 c - g, exact
+        const float emg = __builtin_fmaf(c1, a, -g) - eg;      // c1 a - c2 c
+        const float epg = __builtin_fmaf(c1, a, g);            // c1 a + c2 c
+        const float fph = (w1 + w2) + (w3 + w4);
+        const float fmh = (w1 - w3) + (w2 - w4);
+        return s + 0.5f * __builtin_fmaf(emg, fph, epg * fmh);
+    }
+    // d1 m (w + m) - d2 p (w + p): F - H = m - p, F + H = (w + m) + (w + p)
+    static __device__ __forceinline__ float add_vself(float s, float d1, float m, float w, float d2, float p) {
+        const float g = d2 * p;
+        const float eg = __builtin_fmaf(d2, p, -g);
+        const float emg = __builtin_fmaf(d1, m, -g) - eg;
+        const float epg = __builtin_fmaf(d1, m, g);
+        return s + 0.5f * __builtin_fmaf(emg, (w + m) + (w + p), epg * (m - p));
+    }
+};
+
+// ---------------------------------------------------------------- FP32: Kahan product differences
+struct ArithKahan {
+    using T = float;
+    // a b - c d: w = RN(c d); e = c d - w exactly; RN(RN(a b - w) - e)
+    static __device__ __forceinline__ float pdiff(float a, float b, float c, float d) {
+        const float w = c * d;
+        const float e = __builtin_fmaf(c, d, -w);
+        return __builtin_fmaf(a, b, -w) - e;
+    }
+    static __device__ __forceinline__ float self_flux(float A, float U, float C) { return (A - C) * ((U + A) + C); }
+    static __device__ __forceinline__ float cross_flux(float E, float v1, float v2, float G, float v3, float v4) {
+        return pdiff(E, v1 + v2, G, v3 + v4);
+    }
+    static __device__ __forceinline__ float add_vert(float s, float c1, float a, float w1, float w2, float c2, float c,
+                                                     float w3, float w4) {
+        return s + pdiff(c1 * a, w1 + w2, c2 * c, w3 + w4);
+    }
+    static __device__ __forceinline__ float add_vself(float s, float d1, float m, float w, float d2, float p) {
+        return s + pdiff(d1 * m, w + m, d2 * p, w + p);
+    }
+};
+
+// Policy of each storage type.
+template <typename ST> struct arith_of { using type = ArithKahan; };
+template <> struct arith_of<double> { using type = ArithF64; };
+template <> struct arith_of<float> { using type = ArithSplit; };
+
+// Coefficients of one point.  Each output's x and y coefficients are uniform
+// over the domain; the vertical pair is per level.  For 16-bit storage the
+// per-field power-of-two scales are folded in (term coefficient x out_scale /
+// (scale of its two fields)), so the arithmetic runs on stored values and
+// yields stored outputs; the folding is exact.
+template <typename CT>
+struct PointCoefs {
+    CT xu, yu, z1u, z2u;   // su: tcx, tcy, tzc1(k), tzc2(k)
+    CT yv, xv, z1v, z2v;   // sv: tcy, tcx, tzc1(k), tzc2(k)
+    CT xw, yw, z1w, z2w;   // sw: tcx, tcy, tzd1(k), tzd2(k)
+};
+
+// GUARDED: reads above the column top only when k < nz (global-memory
+// accessors, where level nz+1 may lie outside the array).  Unguarded (LDS
+// windows, where every such read stays inside the staged window): all reads
+// are issued unconditionally and the column-top and k = 1 results are picked
+// by selects, so the code is straight-line and two points of one thread can
+// share their reads.
+template <typename AR, bool GUARDED, typename Acc, typename CT = typename AR::T>
+__device__ __forceinline__ void pw_point(const Acc& A, int k, int nz, const PointCoefs<CT>& c, CT& su, CT& sv,
+                                         CT& sw) {
+    if constexpr (GUARDED) {
+        if (k < 2) {
+            su = CT(0);
+            sv = CT(0);
+            sw = CT(0);
+            return;
+        }
     }
     const CT u0 = A.template u<0, 0, 0>();
     const CT v0 = A.template v<0, 0, 0>();
@@ -107,34 +161,49 @@ __device__ __forceinline__ void pw_point(const Acc& A, int k, int nz, CT tcx, CT
     const CT v_zm = A.template v<-1, 0, 0>();
 
     // su: Listing 1 -- x term, y term, then the vertical term
-    CT s = tcx * self_flux(u_xm, u0, u_xp);
-    s = s + tcy * cross_flux(u_ym, v_ym, A.template v<0, -1, 1>(), u_yp, v0, v_xp);
+    CT s = c.xu * AR::self_flux(u_xm, u0, u_xp);
+    s = s + c.yu * AR::cross_flux(u_ym, v_ym, A.template v<0, -1, 1>(), u_yp, v0, v_xp);
     // sv: mirror of su, own-direction (y) term first
-    CT t = tcy * self_flux(v_ym, v0, v_yp);
-    t = t + tcx * cross_flux(v_xm, u_xm, A.template u<0, 1, -1>(), v_xp, u0, u_yp);
+    CT t = c.yv * AR::self_flux(v_ym, v0, v_yp);
+    t = t + c.xv * AR::cross_flux(v_xm, u_xm, A.template u<0, 1, -1>(), v_xp, u0, u_yp);
 
     const CT w_u_lo = A.template w<-1, 0, 1>();   // w(k-1, j, i+1): lower z face of u
     const CT w_v_lo = A.template w<-1, 1, 0>();   // w(k-1, j+1, i): lower z face of v
-    if (k < nz) {
+    // column top: the upper vertical flux of su and sv is dropped; sw = 0
+    auto top = [&](CT& a, CT& b) {
+        a = s + c.z1u * u_zm * (w_zm + w_u_lo);
+        b = t + c.z1v * v_zm * (w_zm + w_v_lo);
+    };
+    auto full = [&](CT& a, CT& b, CT& r) {
         const CT w_xp = A.template w<0, 0, 1>();
         const CT w_yp = A.template w<0, 1, 0>();
         const CT u_zp = A.template u<1, 0, 0>();
         const CT v_zp = A.template v<1, 0, 0>();
         const CT w_zp = A.template w<1, 0, 0>();
-        s = add_vert(s, z.c1, u_zm, w_zm, w_u_lo, z.c2, u_zp, w0, w_xp);
-        t = add_vert(t, z.c1, v_zm, w_zm, w_v_lo, z.c2, v_zp, w0, w_yp);
+        a = AR::add_vert(s, c.z1u, u_zm, w_zm, w_u_lo, c.z2u, u_zp, w0, w_xp);
+        b = AR::add_vert(t, c.z1v, v_zm, w_zm, w_v_lo, c.z2v, v_zp, w0, w_yp);
         // sw: x and y terms with u, v summed over levels k, k+1; then w along z
-        CT r = tcx * cross_flux(A.template w<0, 0, -1>(), u_xm, A.template u<1, 0, -1>(), w_xp, u0, u_zp);
-        r = r + tcy * cross_flux(A.template w<0, -1, 0>(), v_ym, A.template v<1, -1, 0>(), w_yp, v0, v_zp);
-        sw = add_vself(r, z.d1, w_zm, w0, z.d2, w_zp);
+        CT q = c.xw * AR::cross_flux(A.template w<0, 0, -1>(), u_xm, A.template u<1, 0, -1>(), w_xp, u0, u_zp);
+        q = q + c.yw * AR::cross_flux(A.template w<0, -1, 0>(), v_ym, A.template v<1, -1, 0>(), w_yp, v0, v_zp);
+        r = AR::add_vself(q, c.z1w, w_zm, w0, c.z2w, w_zp);
+    };
+    if constexpr (GUARDED) {
+        if (k < nz) {
+            full(su, sv, sw);
+        } else {
+            top(su, sv);
+            sw = CT(0);
+        }
     } else {
-        // column top: the upper vertical flux of su and sv is dropped; sw = 0
-        s = s + z.c1 * u_zm * (w_zm + w_u_lo);
-        t = t + z.c1 * v_zm * (w_zm + w_v_lo);
-        sw = CT(0);
+        CT fa, fb, fr, ta, tb;
+        full(fa, fb, fr);
+        top(ta, tb);
+        const bool in = k < nz;
+        const bool live = k >= 2;
+        su = live ? (in ? fa : ta) : CT(0);
+        sv = live ? (in ? fb : tb) : CT(0);
+        sw = (live && in) ? fr : CT(0);
     }
-    su = s;
-    sv = t;
 }
 
 }  // namespace pw

@@ -36,14 +36,9 @@ template <> __device__ __forceinline__ double from_compute<double>(double x) { r
 template <> __device__ __forceinline__ float from_compute<float>(float x) { return x; }
 template <> __device__ __forceinline__ f16_t from_compute<f16_t>(float x) { return static_cast<f16_t>(x); }
 template <> __device__ __forceinline__ bf16_t from_compute<bf16_t>(float x) {
-    uint32_t u = __float_as_uint(x);
+    const __bf16 h = static_cast<__bf16>(x);   // v_cvt_pk_bf16_f32: round to nearest even
     bf16_t r;
-    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) {
-        r.bits = static_cast<uint16_t>((u >> 16) | 0x0040u);   // quiet NaN, sign kept
-    } else {
-        u += 0x7fffu + ((u >> 16) & 1u);                          // ties to even
-        r.bits = static_cast<uint16_t>(u >> 16);
-    }
+    __builtin_memcpy(&r.bits, &h, 2);
     return r;
 }
 
