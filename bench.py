@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--skip-cpu", action="store_true", help="do not time the CPU oracle (no error figures)")
     ap.add_argument("--skip-variants", action="store_true", help="FP64 only")
     ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-streaming", action="store_true", help="no host-resident (PCIe-inclusive) runs")
+    ap.add_argument("--skip-power", action="store_true", help="no board-power sampling")
+    ap.add_argument("--streaming-536m", action="store_true",
+                    help="also stream the 536M-point (2048x4096x64) domain, the paper's largest")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0: all usable cores, max 16)")
     ap.add_argument("--copy-probe", type=float, default=0.0,
                     help="only time a plain device copy of this many GB per direction (HBM calibration)")
@@ -203,15 +207,14 @@ def main():
     kept = {}
     if not args.skip_variants:
         variants = {}
-        for storage in (B.F32, B.BF16, B.F16):
+        for storage in (B.F32, B.BF16, B.F16, B.I16):
             name = B.DTYPE_NAMES[storage]
-            dt = B.torch_dtype(storage)
-            if storage == B.F16:
+            if storage in (B.F16, B.I16):
                 ins, outs_s = inputs.fp16_input_scales(p), inputs.fp16_output_scales(p)
             else:
                 ins, outs_s = (1.0, 1.0, 1.0), (1.0, 1.0, 1.0)
             sc = B.make_scales(ins, outs_s)
-            fu, fv, fw = (torch.from_numpy(a).to(dev).mul_(s).to(dt) for a, s in zip((p.u, p.v, p.w), ins))
+            fu, fv, fw = (B.to_storage(a, storage, s, dev) for a, s in zip((p.u, p.v, p.w), ins))
             dd = B.DeviceDomain(fu, fv, fw, c.tcx, c.tcy, *tz, scales=sc)
             pl = B.Plan(storage, [B.shape_of(fu)], tuning)
             vms = time_steps(lambda: dd.run(pl, stream), args.steps, args.warmup, stream)
@@ -230,6 +233,17 @@ def main():
     batches = {}
     if not args.skip_batched:
         result["batched"], batches = batched_leg(dev, stream, gpts, log)
+
+    # ---------------- board power during the FP64 kernel ----------------
+    if not args.skip_power:
+        result["power"] = power_leg(lambda: d64.run(plan, stream), ms, p.npoints, stream, log)
+
+    # ---------------- host-resident domains, transfers included ----------------
+    if not args.skip_streaming:
+        sizes = [("pw512", inputs.workload("pw512")), ("pw2048", p)]
+        if args.streaming_536m:
+            sizes.append(("pw2048x4096", inputs.make_problem(2048, 4096, 64, inputs.SEED_BASE + 5)))
+        result["streaming"] = streaming_leg(sizes, log)
 
     # ---------------- CPU oracle baseline (the only leg that runs the oracle) ----------------
     if not args.skip_cpu:
@@ -250,6 +264,102 @@ def main():
             log("batched", name, "error", result["batched"][name]["max_rel_err_sampled"])
 
     print(json.dumps(result), flush=True)
+
+
+def read_power_w():
+    """Current socket power of GPU 0 in W from amd-smi, or None."""
+    import subprocess
+    try:
+        out = subprocess.run(["amd-smi", "metric", "-g", "0", "-p", "--json"], capture_output=True, text=True,
+                             timeout=20).stdout
+        data = json.loads(out)
+        rec = data["gpu_data"][0] if isinstance(data, dict) else data[0]
+        return float(rec["power"]["socket_power"]["value"])
+    except Exception:
+        return None
+
+
+def power_leg(step, ms_per_step, npoints, stream, log, seconds=6.0):
+    """Mean board power while the kernel runs back to back for `seconds`, and
+    the idle power before it; energy efficiency in Gpoints per joule."""
+    import threading
+    import torch
+    idle = [x for x in (read_power_w() for _ in range(3)) if x is not None]
+    if not idle:
+        return {"available": False, "reason": "amd-smi socket power not readable"}
+    samples, stop = [], threading.Event()
+
+    def poll():
+        while not stop.is_set():
+            w = read_power_w()
+            if w is not None:
+                samples.append((time.perf_counter(), w))
+
+    n = max(1, int(seconds * 1e3 / ms_per_step))
+    torch.cuda.synchronize()
+    th = threading.Thread(target=poll, daemon=True)
+    t0 = time.perf_counter()
+    th.start()
+    done = 0
+    while done < n:
+        for _ in range(min(200, n - done)):
+            step()
+        done += min(200, n - done)
+        torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stop.set()
+    th.join(timeout=30)
+    busy = [w for (t, w) in samples if t0 + 0.5 <= t <= t1]
+    if not busy:
+        return {"available": False, "reason": "no power sample during the run"}
+    mean_w = sum(busy) / len(busy)
+    gpts = n * npoints / (t1 - t0) / 1e9
+    rec = {"available": True, "source": "amd-smi metric -p (socket_power)", "idle_w": round(sum(idle) / len(idle), 1),
+           "busy_w": round(mean_w, 1), "samples": len(busy), "seconds": round(t1 - t0, 2),
+           "gpoints_per_s": round(gpts, 2), "gpoints_per_joule": round(gpts / mean_w, 4)}
+    log("power", rec)
+    return rec
+
+
+def streaming_leg(sizes, log, chunks=(32, 64, 128), reps=3):
+    """Host-resident domains in pinned memory: one bulk round trip (copy in,
+    compute, copy out) against x-slabs whose transfers overlap the kernel
+    (paper Sec. IV).  End-to-end Gpoints/s including the transfers."""
+    import torch
+    from paper_2107_13500_amd import binding as B
+    out = {}
+    for name, p in sizes:
+        t0 = time.perf_counter()
+        ins = [torch.from_numpy(a).pin_memory() for a in (p.u, p.v, p.w)]
+        outs = [torch.zeros(p.u.shape, dtype=torch.float64, pin_memory=True) for _ in range(3)]
+        tz = [torch.from_numpy(x).clone() for x in p.coeffs.arrays()]
+        log("streaming %s: pinned host buffers in %.1f s" % (name, time.perf_counter() - t0))
+        shape = B.shape_of(ins[0])
+        moved = 8 * (3 * (p.nx + 2) * (p.ny + 2) * p.nz + 3 * p.npoints)
+
+        def run_mode(**kw):
+            sp = B.StreamPlan(B.F64, shape, **kw)
+            sp.run(*ins, *outs, p.coeffs.tcx, p.coeffs.tcy, *tz)   # warm-up
+            ts = []
+            for _ in range(reps):
+                a = time.perf_counter()
+                sp.run(*ins, *outs, p.coeffs.tcx, p.coeffs.tcy, *tz)
+                ts.append(time.perf_counter() - a)
+            sp.close()
+            t = sorted(ts)[len(ts) // 2]
+            return {"s": round(t, 5), "gpoints_per_s": round(p.npoints / t / 1e9, 3),
+                    "host_device_gbs": round(moved / t / 1e9, 2)}
+
+        rec = {"points": p.npoints, "host_device_bytes": moved, "bulk": run_mode(bulk=True), "overlapped": {}}
+        for c in chunks:
+            rec["overlapped"]["chunk%d" % c] = run_mode(chunk=c, nbuffers=3)
+        best = min(rec["overlapped"].values(), key=lambda r: r["s"])
+        rec["best_overlapped_gpoints_per_s"] = best["gpoints_per_s"]
+        rec["overlap_speedup"] = round(rec["bulk"]["s"] / best["s"], 3)
+        log("streaming", name, rec)
+        out[name] = rec
+        del ins, outs
+    return out
 
 
 def batched_leg(dev, stream, f64_gpts, log, replays=100):

@@ -30,11 +30,13 @@
  * touched.  The caller fills the input halos (including the corner columns,
  * which sv and su read) before the call.
  *
- * Storage precision: PW_F64 computes in FP64.  PW_F32, PW_BF16 and PW_F16
- * store all six arrays in that type and compute in FP32 with each product
- * difference a*b - c*d evaluated in compensated form (Kahan's fused
- * multiply-add algorithm); the vertical coefficients stay FP64 in memory and
- * are rounded to FP32 once per thread.  For the 16-bit types each field has a
+ * Storage precision: PW_F64 computes in FP64.  PW_F32, PW_BF16, PW_F16 and
+ * PW_I16 store all six arrays in that type and compute in FP32 with every flux
+ * difference in a compensated form: FP32 storage subtracts neighbouring values
+ * first (exact when they are within a factor of two); the 16-bit types, whose
+ * pairwise sums are exact in FP32, use Kahan's fused multiply-add product
+ * difference.  The vertical coefficients stay FP64 in memory and are rounded
+ * to FP32 once per thread.  For the 16-bit types each field has a
  * power-of-two scale: stored = value * scale.
  *
  * Conventions for every entry point:
@@ -72,8 +74,10 @@ enum {
     PW_ERR_PLAN_MISMATCH = -8  /* the arguments do not match the plan */
 };
 
-/* Storage types of the six field arrays. */
-enum { PW_F64 = 0, PW_F32 = 1, PW_BF16 = 2, PW_F16 = 3 };
+/* Storage types of the six field arrays.  PW_I16 is 16-bit fixed point: a
+   signed integer with a per-field power-of-two scale (stored = value * scale,
+   rounded to nearest even and saturated to [-32768, 32767] on output). */
+enum { PW_F64 = 0, PW_F32 = 1, PW_BF16 = 2, PW_F16 = 3, PW_I16 = 4 };
 
 /* Kernel variants (pw_tuning.variant). */
 enum {
@@ -227,6 +231,39 @@ int32_t pw_perturb_batched(const pw_plan *plan, int32_t ndomains,
    not match the plan or a field pointer was NULL.  Synchronous (copies one
    word from the device).  `count` is a host out-pointer. */
 int32_t pw_plan_error_count(const pw_plan *plan, unsigned long long *count);
+
+/* Host-resident domains (paper Sec. IV: the accelerator run with the
+   host<->device transfers included).  A stream plan owns device buffers,
+   three streams and events for one host domain shape:
+     bulk != 0  one round trip: copy the whole domain in, compute, copy the
+                outputs out, in order on one stream (no overlap);
+     bulk == 0  x-slabs of `chunk` planes through a ring of `nbuffers` (2..8)
+                device slab buffers: the inputs of one slab (its planes plus
+                one x-halo plane on each side) are copied in while the
+                previous slab is computed and the one before it is copied
+                out, ordered by events.
+   Requires packed columns (sy == nz).  Allocates; not for use during
+   capture (PW_ERR_CAPTURE).  `tuning` (host or NULL) applies to the slab
+   kernels. */
+typedef struct pw_stream_plan pw_stream_plan;
+int32_t pw_stream_plan_create(pw_stream_plan **plan, int32_t storage, const pw_shape *shape,
+                              int32_t chunk, int32_t nbuffers, int32_t bulk, const pw_tuning *tuning);
+/* Synchronises the device, then frees the plan. */
+int32_t pw_stream_plan_destroy(pw_stream_plan *plan);
+
+/* su, sv, sw of a host-resident domain (same results as pw_advect on the
+   same data).  All pointers are HOST pointers; pinned memory (hipHostMalloc)
+   lets the copies run asynchronously and overlap.  Each array must span the
+   domain's extent; the output halo columns are never written.  Blocks until
+   the outputs are on the host.  Returns PW_ERR_ALIAS if an output overlaps an
+   input. */
+int32_t pw_advect_host(pw_stream_plan *plan,
+                       const void *h_u, const void *h_v, const void *h_w,
+                       void *h_su, void *h_sv, void *h_sw,
+                       double tcx, double tcy,
+                       const double *h_tzc1, const double *h_tzc2,
+                       const double *h_tzd1, const double *h_tzd2,
+                       const pw_scales *scales);
 
 /* Launch-shape autotuner (the batched form's tile shapes: chunk, segment
    length, workgroups per CU; the single-domain variant, chunk and segment).

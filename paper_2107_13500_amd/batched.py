@@ -54,13 +54,12 @@ class DeviceBatch:
             views = [self.pool[o:o + n * esize].view(dt).view(p.nx + 2, p.ny + 2, p.nz) for o in offs[d]]
             if scales is not None:
                 sc = scales[d]
-            elif storage == B.F16:
+            elif storage in (B.F16, B.I16):
                 sc = B.make_scales(inputs.fp16_input_scales(p), inputs.fp16_output_scales(p))
             else:
                 sc = B.make_scales()
             for f, a in enumerate((p.u, p.v, p.w)):
-                s = float(sc.in_scale[f]) if storage in (B.BF16, B.F16) else 1.0
-                views[f].copy_(torch.from_numpy(a * s if s != 1.0 else a).to(self.device).to(dt))
+                views[f].copy_(B.to_storage(a, storage, float(sc.in_scale[f]), self.device))
             tz = [self.coef_pool[ci + q * p.nz: ci + (q + 1) * p.nz] for q in range(4)]
             ci += 4 * p.nz
             self.fields.append(views)
@@ -114,24 +113,16 @@ class DeviceBatch:
         """The same work as ``advect`` as one pw_advect launch per domain."""
         for f, tz, p, sc, pl in zip(self.fields, self.tz, self.problems, self.scales, plans):
             B.advect(pl, *f, p.coeffs.tcx, p.coeffs.tcy, *tz,
-                     scales=sc if self.storage in (B.BF16, B.F16) else None, stream=stream)
+                     scales=sc if self.storage in B.SCALED else None, stream=stream)
 
     def host_fields(self, d: int):
         """u, v, w of domain d copied back as float64 numpy arrays (descaled)."""
-        out = []
-        for f in range(3):
-            a = self.fields[d][f].to("cpu").double().numpy()
-            s = float(self.scales[d].in_scale[f]) if self.storage in (B.BF16, B.F16) else 1.0
-            out.append(a / s if s != 1.0 else a)
-        return out
+        return [B.from_storage(self.fields[d][f], self.storage, float(self.scales[d].in_scale[f]))
+                for f in range(3)]
 
     def host_outputs(self, d: int):
-        out = []
-        for f in range(3):
-            a = self.fields[d][3 + f].to("cpu").double().numpy()
-            s = float(self.scales[d].out_scale[f]) if self.storage in (B.BF16, B.F16) else 1.0
-            out.append(a / s if s != 1.0 else a)
-        return out
+        return [B.from_storage(self.fields[d][3 + f], self.storage, float(self.scales[d].out_scale[f]))
+                for f in range(3)]
 
 
 def autotune(batch: DeviceBatch, candidates: Optional[Sequence[dict]] = None, reps: int = 5):

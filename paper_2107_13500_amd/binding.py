@@ -20,9 +20,10 @@ STATUS_NAMES = {
     -4: "PW_ERR_ALIGNMENT", -5: "PW_ERR_OUT_OF_MEMORY", -6: "PW_ERR_HIP", -7: "PW_ERR_CAPTURE",
     -8: "PW_ERR_PLAN_MISMATCH",
 }
-F64, F32, BF16, F16 = 0, 1, 2, 3
+F64, F32, BF16, F16, I16 = 0, 1, 2, 3, 4
+SCALED = (BF16, F16, I16)
 VARIANT_AUTO, VARIANT_DIRECT, VARIANT_MARCH = 0, 1, 2
-DTYPE_NAMES = {F64: "f64", F32: "f32", BF16: "bf16", F16: "f16"}
+DTYPE_NAMES = {F64: "f64", F32: "f32", BF16: "bf16", F16: "f16", I16: "i16"}
 
 
 class PwShape(ctypes.Structure):
@@ -69,6 +70,11 @@ SIGNATURES = {
     "pw_autotune": (c_int32, [c_int32, POINTER(PwShape), c_int32, c_void_p, c_void_p, POINTER(PwTuning),
                               c_int32, c_int32, POINTER(PwTuning), POINTER(c_float), POINTER(c_float)]),
     "pw_autotune_candidates": (c_int32, [c_int32, POINTER(PwTuning), c_int32]),
+    "pw_stream_plan_create": (c_int32, [POINTER(c_void_p), c_int32, POINTER(PwShape), c_int32, c_int32, c_int32,
+                                        POINTER(PwTuning)]),
+    "pw_stream_plan_destroy": (c_int32, [c_void_p]),
+    "pw_advect_host": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(PwScales)]),
     "pw_probe_copy": (c_int32, [POINTER(c_void_p), POINTER(c_void_p), c_int32, c_int64, c_int32, c_void_p]),
     "pw_status_string": (ctypes.c_char_p, [c_int32]),
     "pw_last_hip_error": (c_int32, []),
@@ -124,7 +130,7 @@ def _torch():
 
 def storage_of(dtype) -> int:
     torch = _torch()
-    table = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16}
+    table = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16, torch.int16: I16}
     if dtype not in table:
         raise TypeError("unsupported field dtype %s" % dtype)
     return table[dtype]
@@ -132,7 +138,28 @@ def storage_of(dtype) -> int:
 
 def torch_dtype(storage: int):
     torch = _torch()
-    return {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16, F16: torch.float16}[storage]
+    return {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16, F16: torch.float16,
+            I16: torch.int16}[storage]
+
+
+def to_storage(a, storage: int, scale: float = 1.0, device=None):
+    """Host float64 numpy array -> tensor of the storage type (scaled; int16
+    rounded to nearest and saturated), optionally moved to `device`."""
+    torch = _torch()
+    t = torch.from_numpy(a)
+    if device is not None:
+        t = t.to(device)
+    if storage in SCALED and scale != 1.0:
+        t = t * scale
+    if storage == I16:
+        t = torch.round(t).clamp_(-32768, 32767)
+    return t.to(torch_dtype(storage))
+
+
+def from_storage(t, storage: int, scale: float = 1.0):
+    """Device/host tensor of a storage type -> float64 numpy array (descaled)."""
+    a = t.double().cpu().numpy()
+    return a / scale if (storage in SCALED and scale != 1.0) else a
 
 
 def stream_handle(stream=None) -> int:
@@ -241,6 +268,38 @@ def probe_copy(srcs, dsts, nbytes: int, workgroups: int = 0, stream=None) -> Non
     sp = (c_void_p * n)(*[t.data_ptr() for t in srcs])
     dp = (c_void_p * n)(*[t.data_ptr() for t in dsts])
     check(lib().pw_probe_copy(sp, dp, n, int(nbytes), int(workgroups), stream_handle(stream)), "pw_probe_copy")
+
+
+class StreamPlan:
+    """Owning wrapper of a pw_stream_plan (host-resident domain)."""
+
+    def __init__(self, storage: int, shape: PwShape, chunk: int = 64, nbuffers: int = 3, bulk: bool = False,
+                 tuning=None):
+        h = c_void_p()
+        t = make_tuning(tuning)
+        check(lib().pw_stream_plan_create(ctypes.byref(h), int(storage), ctypes.byref(shape), int(chunk),
+                                          int(nbuffers), 1 if bulk else 0,
+                                          ctypes.byref(t) if t is not None else None), "pw_stream_plan_create")
+        self.handle = h
+        self.storage = storage
+
+    def run(self, u, v, w, su, sv, sw, tcx, tcy, tzc1, tzc2, tzd1, tzd2, scales: Optional[PwScales] = None):
+        """pw_advect_host on host tensors (blocking)."""
+        check(lib().pw_advect_host(self.handle, u.data_ptr(), v.data_ptr(), w.data_ptr(), su.data_ptr(),
+                                   sv.data_ptr(), sw.data_ptr(), float(tcx), float(tcy), tzc1.data_ptr(),
+                                   tzc2.data_ptr(), tzd1.data_ptr(), tzd2.data_ptr(),
+                                   ctypes.byref(scales) if scales is not None else None), "pw_advect_host")
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            check(lib().pw_stream_plan_destroy(self.handle), "pw_stream_plan_destroy")
+            self.handle = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def domain_args_tensor(records: Sequence[PwDomainArgs], device):

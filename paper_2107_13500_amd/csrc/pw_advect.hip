@@ -32,12 +32,15 @@ int64_t elem_bytes(int32_t storage) {
         case PW_F64: return 8;
         case PW_F32: return 4;
         case PW_BF16:
-        case PW_F16: return 2;
+        case PW_F16:
+        case PW_I16: return 2;
         default: return 0;
     }
 }
 
 int64_t compute_bytes(int32_t storage) { return storage == PW_F64 ? 8 : 4; }
+
+bool scaled_storage(int32_t storage) { return storage == PW_BF16 || storage == PW_F16 || storage == PW_I16; }
 
 int32_t normalize_shape(const pw_shape& in, pw_shape* out) {
     pw_shape s = in;
@@ -175,6 +178,7 @@ hipError_t launch_domain(int32_t storage, const DomainArgs& d, const Launch& L, 
         case PW_F32: return launch_typed<float>(d, L, vec, stream);
         case PW_BF16: return launch_typed<bf16_t>(d, L, vec, stream);
         case PW_F16: return launch_typed<f16_t>(d, L, vec, stream);
+        case PW_I16: return launch_typed<fx16_t>(d, L, vec, stream);
         default: return hipErrorInvalidValue;
     }
 }
@@ -342,7 +346,7 @@ int32_t fill_domain_args(int32_t storage, const pw_shape& s, const void* u, cons
     d.tzd2 = tzd2;
     float in_s[3] = {1.0f, 1.0f, 1.0f};
     float out_s[3] = {1.0f, 1.0f, 1.0f};
-    if (scales && (storage == PW_BF16 || storage == PW_F16)) {
+    if (scales && scaled_storage(storage)) {
         for (int f = 0; f < 3; ++f) {
             const float a = scales->in_scale[f];
             const float b = scales->out_scale[f];

@@ -228,6 +228,7 @@ int batched_occupancy(int32_t storage, int32_t chunk, int64_t lds_bytes) {
         case PW_F32: return occupancy_typed<float>(chunk, lds_bytes);
         case PW_BF16: return occupancy_typed<bf16_t>(chunk, lds_bytes);
         case PW_F16: return occupancy_typed<f16_t>(chunk, lds_bytes);
+        case PW_I16: return occupancy_typed<fx16_t>(chunk, lds_bytes);
         default: return 0;
     }
 }
@@ -367,6 +368,7 @@ int32_t pw_advect_batched(const pw_plan* plan, int32_t ndomains, const pw_domain
         case PW_F32: e = dispatch_batched<float>(plan, d_args, s); break;
         case PW_BF16: e = dispatch_batched<bf16_t>(plan, d_args, s); break;
         case PW_F16: e = dispatch_batched<f16_t>(plan, d_args, s); break;
+        case PW_I16: e = dispatch_batched<fx16_t>(plan, d_args, s); break;
         default: return PW_ERR_UNSUPPORTED;
     }
     if (e != hipSuccess) return report_hip(e);
@@ -386,6 +388,7 @@ int32_t pw_fill_halo_batched(const pw_plan* plan, int32_t ndomains, const pw_dom
         case PW_F32: hipLaunchKernelGGL(pw_halo_kernel<float>, grid, dim3(256), 0, s, tb, d_args); break;
         case PW_BF16: hipLaunchKernelGGL(pw_halo_kernel<bf16_t>, grid, dim3(256), 0, s, tb, d_args); break;
         case PW_F16: hipLaunchKernelGGL(pw_halo_kernel<f16_t>, grid, dim3(256), 0, s, tb, d_args); break;
+        case PW_I16: hipLaunchKernelGGL(pw_halo_kernel<fx16_t>, grid, dim3(256), 0, s, tb, d_args); break;
         default: return PW_ERR_UNSUPPORTED;
     }
     hipError_t e = hipGetLastError();
@@ -414,6 +417,9 @@ int32_t pw_perturb_batched(const pw_plan* plan, int32_t ndomains, const pw_domai
             break;
         case PW_F16:
             hipLaunchKernelGGL(pw_perturb_kernel<f16_t>, grid, dim3(256), 0, s, tb, d_args, seed, d_call, amplitude);
+            break;
+        case PW_I16:
+            hipLaunchKernelGGL(pw_perturb_kernel<fx16_t>, grid, dim3(256), 0, s, tb, d_args, seed, d_call, amplitude);
             break;
         default: return PW_ERR_UNSUPPORTED;
     }

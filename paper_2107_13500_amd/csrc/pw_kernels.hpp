@@ -58,6 +58,7 @@ struct MarchGeom {
 template <typename ST> struct is16 { static constexpr bool value = false; };
 template <> struct is16<bf16_t> { static constexpr bool value = true; };
 template <> struct is16<f16_t> { static constexpr bool value = true; };
+template <> struct is16<fx16_t> { static constexpr bool value = true; };
 
 // Folded coefficients (see DomainArgs) from tcx, tcy and the storage scales.
 __host__ __device__ inline void fold_coefficients(double tcx, double tcy, const float in_scale[3],

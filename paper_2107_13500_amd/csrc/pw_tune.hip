@@ -82,7 +82,7 @@ extern "C" int32_t pw_autotune(int32_t storage, const pw_shape* shapes, int32_t 
         auto run = [&]() -> int32_t {
             if (batched) return pw_advect_batched(plan, ndomains, d_args, stream);
             const pw_domain_args& a = h_args[0];
-            const pw_scales* sc = (storage == PW_BF16 || storage == PW_F16) ? &a.scales : nullptr;
+            const pw_scales* sc = pw::scaled_storage(storage) ? &a.scales : nullptr;
             return pw_advect(plan, a.u, a.v, a.w, a.su, a.sv, a.sw, a.tcx, a.tcy, a.tzc1, a.tzc2, a.tzd1, a.tzd2,
                              sc, stream);
         };

@@ -6,11 +6,15 @@
 
 namespace pw {
 
-// bfloat16 stored as its raw 16 bits; FP16 as the compiler's _Float16.
+// bfloat16 stored as its raw 16 bits; FP16 as the compiler's _Float16;
+// 16-bit fixed point as a signed integer (value = stored / scale).
 struct bf16_t {
     uint16_t bits;
 };
 using f16_t = _Float16;
+struct fx16_t {
+    int16_t v;
+};
 
 // ---------------------------------------------------------------------------
 // compute type of each storage type
@@ -24,6 +28,7 @@ template <> struct compute_of<double> { using type = double; };
 __device__ __forceinline__ double to_compute(double x) { return x; }
 __device__ __forceinline__ float to_compute(float x) { return x; }
 __device__ __forceinline__ float to_compute(f16_t x) { return static_cast<float>(x); }
+__device__ __forceinline__ float to_compute(fx16_t x) { return static_cast<float>(x.v); }
 __device__ __forceinline__ float to_compute(bf16_t x) {
     return __uint_as_float(static_cast<uint32_t>(x.bits) << 16);
 }
@@ -35,6 +40,13 @@ template <typename ST> __device__ __forceinline__ ST from_compute(typename compu
 template <> __device__ __forceinline__ double from_compute<double>(double x) { return x; }
 template <> __device__ __forceinline__ float from_compute<float>(float x) { return x; }
 template <> __device__ __forceinline__ f16_t from_compute<f16_t>(float x) { return static_cast<f16_t>(x); }
+// round to nearest even, saturate to the int16 range (NaN becomes -32768)
+template <> __device__ __forceinline__ fx16_t from_compute<fx16_t>(float x) {
+    const float r = __builtin_fminf(__builtin_fmaxf(__builtin_rintf(x), -32768.0f), 32767.0f);
+    fx16_t y;
+    y.v = static_cast<int16_t>(static_cast<int>(r));
+    return y;
+}
 template <> __device__ __forceinline__ bf16_t from_compute<bf16_t>(float x) {
     const __bf16 h = static_cast<__bf16>(x);   // v_cvt_pk_bf16_f32: round to nearest even
     bf16_t r;

@@ -13,7 +13,8 @@ from paper_2107_13500_amd import inputs
 DEV = "cuda:0"
 F64_TOL = 1e-12          # max-norm relative, per field
 
-SENTINEL = {torch.float64: -7.25e300, torch.float32: -7.25e30, torch.bfloat16: -7.25e30, torch.float16: -6.0e4}
+SENTINEL = {torch.float64: -7.25e300, torch.float32: -7.25e30, torch.bfloat16: -7.25e30, torch.float16: -6.0e4,
+            torch.int16: -32000}
 
 
 def say(*a):
@@ -21,15 +22,10 @@ def say(*a):
     sys.stdout.flush()
 
 
-def to_storage(a: np.ndarray, dtype, scale: float = 1.0):
-    t = torch.from_numpy(a * scale if scale != 1.0 else a)
-    return t.to(dtype)
-
-
 def device_domain(p: inputs.Problem, storage: int = B.F64, scales=None, sentinel=True):
     dt = B.torch_dtype(storage)
     ins = (1.0, 1.0, 1.0) if scales is None else tuple(scales.in_scale)
-    u, v, w = (to_storage(a, dt, s).to(DEV) for a, s in zip((p.u, p.v, p.w), ins))
+    u, v, w = (B.to_storage(a, storage, s, DEV) for a, s in zip((p.u, p.v, p.w), ins))
     c = p.coeffs
     tz = [torch.from_numpy(x).to(DEV) for x in c.arrays()]
     d = B.DeviceDomain(u, v, w, c.tcx, c.tcy, *tz, scales=scales)

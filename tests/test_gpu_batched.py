@@ -35,7 +35,7 @@ def single_outputs(batch, d, tuning):
     plan = B.Plan(batch.storage, [batch.records[d].shape], tuning)
     p = batch.problems[d]
     B.advect(plan, f[0], f[1], f[2], *outs, p.coeffs.tcx, p.coeffs.tcy, *batch.tz[d],
-             scales=batch.scales[d] if batch.storage in (B.BF16, B.F16) else None)
+             scales=batch.scales[d] if batch.storage in B.SCALED else None)
     torch.cuda.synchronize()
     return outs
 
@@ -63,7 +63,7 @@ def test_batched_f64_parity_and_bit_identity(tuning):
             assert torch.equal(a[1:-1, 1:-1], b[1:-1, 1:-1]), "domain %d differs from pw_advect" % d
 
 
-@pytest.mark.parametrize("storage", [B.F32, B.BF16, B.F16], ids=["f32", "bf16", "f16"])
+@pytest.mark.parametrize("storage", [B.F32, B.BF16, B.F16, B.I16], ids=["f32", "bf16", "f16", "i16"])
 def test_batched_reduced_storage_matches_single_calls(storage):
     probs = small_problems(seed=400)
     batch = BT.DeviceBatch(probs, storage, DEV)

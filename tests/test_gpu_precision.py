@@ -18,42 +18,47 @@ from paper_2107_13500_amd import inputs
 pytestmark = pytest.mark.gpu
 
 UNIT_ROUNDOFF = {B.F32: 2.0 ** -24, B.BF16: 2.0 ** -8, B.F16: 2.0 ** -11}
-ORIG_BOUND = {B.F32: 2e-6, B.BF16: 2e-2, B.F16: 3e-3}
+ORIG_BOUND = {B.F32: 2e-6, B.BF16: 2e-2, B.F16: 3e-3, B.I16: 3e-3}
 
 
 def run_storage(p, storage, tuning=None):
-    dt = B.torch_dtype(storage)
-    if storage == B.F16:
+    if storage in (B.F16, B.I16):
         ins, outs = inputs.fp16_input_scales(p), inputs.fp16_output_scales(p)
     else:
         ins, outs = (1.0, 1.0, 1.0), (1.0, 1.0, 1.0)
     sc = B.make_scales(ins, outs)
-    fields = [torch.from_numpy(a * s).to(dt).to(DEV) for a, s in zip((p.u, p.v, p.w), ins)]
+    fields = [B.to_storage(a, storage, s, DEV) for a, s in zip((p.u, p.v, p.w), ins)]
     tz = [torch.from_numpy(x).to(DEV) for x in p.coeffs.arrays()]
     d = B.DeviceDomain(*fields, p.coeffs.tcx, p.coeffs.tcy, *tz, scales=sc)
     plan = B.Plan(storage, [B.shape_of(fields[0])], tuning)
     d.run(plan)
     torch.cuda.synchronize()
-    got = [o.double().cpu().numpy() / s for o, s in zip(d.outputs, outs)]
-    deq = [f.double().cpu().numpy() / s for f, s in zip(fields, ins)]
-    return got, deq
+    got = [B.from_storage(o, storage, s) for o, s in zip(d.outputs, outs)]
+    deq = [B.from_storage(f, storage, s) for f, s in zip(fields, ins)]
+    return got, deq, outs
 
 
-@pytest.mark.parametrize("storage", [B.F32, B.BF16, B.F16], ids=["f32", "bf16", "f16"])
+@pytest.mark.parametrize("storage", [B.F32, B.BF16, B.F16, B.I16], ids=["f32", "bf16", "f16", "i16"])
 @pytest.mark.parametrize("shape", [(64, 64, 64), (37, 29, 96), (9, 5, 128)], ids=lambda s: "x".join(map(str, s)))
 def test_reduced_storage_error_bounds(storage, shape):
     p = inputs.make_problem(*shape, seed=1234 + shape[0])
-    got, deq = run_storage(p, storage)
+    got, deq, out_scales = run_storage(p, storage)
     ref_orig = oracle.advect_problem(p)
     c = p.coeffs
     ref_deq = oracle.advect(*deq, c.tcx, c.tcy, *c.arrays())
-    for name, g, ro, rd in zip(("su", "sv", "sw"), got, ref_orig, ref_deq):
+    for name, g, ro, rd, os_ in zip(("su", "sv", "sw"), got, ref_orig, ref_deq, out_scales):
         gi = g[1:-1, 1:-1]
         assert np.all(gi[:, :, 0] == 0.0)
         e_orig = max_rel(gi, ro[1:-1, 1:-1])
         e_deq = max_rel(gi, rd[1:-1, 1:-1])
         say(B.DTYPE_NAMES[storage], shape, name, "vs original %.3e, vs dequantised %.3e" % (e_orig, e_deq))
-        assert e_deq <= UNIT_ROUNDOFF[storage] + 2e-6, "%s arithmetic error %.3e" % (name, e_deq)
+        if storage == B.I16:
+            # output quantum 1/out_scale, rounded to nearest: half a quantum
+            # relative to the largest output
+            bound = 0.5 / (os_ * np.max(np.abs(rd[1:-1, 1:-1])))
+        else:
+            bound = UNIT_ROUNDOFF[storage]
+        assert e_deq <= bound + 2e-6, "%s arithmetic error %.3e > %.3e" % (name, e_deq, bound)
         assert e_orig <= ORIG_BOUND[storage], "%s error vs FP64 oracle %.3e" % (name, e_orig)
 
 
@@ -69,7 +74,7 @@ def test_fp32_difference_first_beats_naive_fp32_on_cancelling_fields():
     w = (0.01 * rng.standard_normal(shp)).astype(np.float32).astype(np.float64)
     co = inputs.coefficients(inputs.vertical_grid(nz), 50.0, 50.0)
     p = inputs.Problem(nx, ny, nz, u, v, w, co, inputs.vertical_grid(nz))
-    got, deq = run_storage(p, B.F32)
+    got, deq, _ = run_storage(p, B.F32)
     ref = oracle.advect(u, v, w, co.tcx, co.tcy, *co.arrays())
     F = rule.Fields(u, v, w, co.tcx, co.tcy, *co.arrays(), conv=np.float32)
     naive = {n: np.zeros(shp) for n in "uvw"}

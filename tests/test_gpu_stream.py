@@ -1,0 +1,104 @@
+"""Host-resident domains through pw_advect_host (GPU).
+
+The slab pipeline and the bulk round trip must give exactly what pw_advect
+gives on the same data already in device memory (the same kernel arithmetic
+per point), match the oracle to 1e-12, and leave the host outputs' halo
+columns untouched.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_helpers import DEV, F64_TOL, max_rel, say
+from paper_2107_13500_amd import binding as B
+from paper_2107_13500_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+HOST_SENTINEL = -5.5e300
+
+
+def host_arrays(p, pinned=True, storage=B.F64):
+    dt = B.torch_dtype(storage)
+    ins = [torch.from_numpy(a).to(dt) for a in (p.u, p.v, p.w)]
+    if pinned:
+        ins = [t.pin_memory() for t in ins]
+    outs = [torch.full(p.u.shape, HOST_SENTINEL if storage == B.F64 else -7.0e30, dtype=dt, pin_memory=pinned)
+            for _ in range(3)]
+    tz = [torch.from_numpy(x).clone() for x in p.coeffs.arrays()]
+    return ins, outs, tz
+
+
+def device_reference(p, storage=B.F64):
+    dt = B.torch_dtype(storage)
+    u, v, w = (torch.from_numpy(a).to(dt).to(DEV) for a in (p.u, p.v, p.w))
+    tz = [torch.from_numpy(x).to(DEV) for x in p.coeffs.arrays()]
+    d = B.DeviceDomain(u, v, w, p.coeffs.tcx, p.coeffs.tcy, *tz)
+    d.run(B.Plan(storage, [B.shape_of(u)]))
+    torch.cuda.synchronize()
+    return [o.cpu() for o in d.outputs]
+
+
+@pytest.mark.parametrize("shape", [(37, 29, 64), (20, 9, 96), (13, 6, 128), (5, 4, 30)],
+                         ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("mode", [dict(chunk=1, nbuffers=2), dict(chunk=5, nbuffers=3), dict(chunk=16, nbuffers=2),
+                                  dict(bulk=True)], ids=["c1b2", "c5b3", "c16b2", "bulk"])
+def test_host_domain_matches_device_call_and_oracle(shape, mode):
+    p = inputs.make_problem(*shape, seed=4321 + shape[0])
+    ins, outs, tz = host_arrays(p)
+    sp = B.StreamPlan(B.F64, B.shape_of(ins[0]), **mode)
+    sp.run(*ins, *outs, p.coeffs.tcx, p.coeffs.tcy, *tz)
+    dev = device_reference(p)
+    ref = oracle.advect_problem(p)
+    for o, dref, r in zip(outs, dev, ref):
+        a = o.numpy()
+        for face in (a[0], a[-1], a[:, 0], a[:, -1]):
+            assert np.all(face == HOST_SENTINEL), "host output halo written"
+        assert torch.equal(o[1:-1, 1:-1], dref[1:-1, 1:-1]), "differs from the device-resident call"
+        assert max_rel(a[1:-1, 1:-1], r[1:-1, 1:-1]) <= F64_TOL
+    sp.close()
+
+
+def test_pageable_host_memory_and_fp32_storage():
+    p = inputs.make_problem(24, 17, 64, seed=99)
+    ins, outs, tz = host_arrays(p, pinned=False, storage=B.F32)
+    sp = B.StreamPlan(B.F32, B.shape_of(ins[0]), chunk=7, nbuffers=3)
+    sp.run(*ins, *outs, p.coeffs.tcx, p.coeffs.tcy, *tz)
+    dev = device_reference(p, B.F32)
+    for o, dref in zip(outs, dev):
+        assert torch.equal(o[1:-1, 1:-1], dref[1:-1, 1:-1])
+
+
+def test_repeated_calls_reuse_the_plan():
+    p = inputs.make_problem(40, 12, 64, seed=7)
+    ins, outs, tz = host_arrays(p)
+    sp = B.StreamPlan(B.F64, B.shape_of(ins[0]), chunk=8, nbuffers=2)
+    sp.run(*ins, *outs, p.coeffs.tcx, p.coeffs.tcy, *tz)
+    first = [o.clone() for o in outs]
+    for _ in range(3):
+        sp.run(*ins, *outs, p.coeffs.tcx, p.coeffs.tcy, *tz)
+    for a, b in zip(first, outs):
+        assert torch.equal(a, b)
+
+
+def test_stream_plan_argument_checks():
+    l = B.lib()
+    h = ctypes.c_void_p()
+    padded = B.PwShape(8, 6, 16, 0, 20, 0)
+    assert l.pw_stream_plan_create(ctypes.byref(h), B.F64, ctypes.byref(padded), 4, 2, 0, None) == -2
+    ok = B.PwShape(8, 6, 16, 0, 0, 0)
+    assert l.pw_stream_plan_create(ctypes.byref(h), B.F64, ctypes.byref(ok), 0, 2, 0, None) == -1
+    assert l.pw_stream_plan_create(ctypes.byref(h), B.F64, ctypes.byref(ok), 4, 1, 0, None) == -1
+    assert l.pw_stream_plan_create(ctypes.byref(h), 9, ctypes.byref(ok), 4, 2, 0, None) == -2
+    p = inputs.make_problem(8, 6, 16, seed=3)
+    ins, outs, tz = host_arrays(p)
+    sp = B.StreamPlan(B.F64, B.shape_of(ins[0]), chunk=4, nbuffers=2)
+    st = l.pw_advect_host(sp.handle, ins[0].data_ptr(), ins[1].data_ptr(), ins[2].data_ptr(), ins[0].data_ptr(),
+                          outs[1].data_ptr(), outs[2].data_ptr(), 0.01, 0.01, *[t.data_ptr() for t in tz], None)
+    assert st == -3
+    st = l.pw_advect_host(sp.handle, None, ins[1].data_ptr(), ins[2].data_ptr(), outs[0].data_ptr(),
+                          outs[1].data_ptr(), outs[2].data_ptr(), 0.01, 0.01, *[t.data_ptr() for t in tz], None)
+    assert st == -1
