@@ -9,17 +9,18 @@ raises if it has not been built.
 __all__ = ["inputs", "metrics", "binding"]
 
 
+#: sources the single-domain kernels are compiled from
+KERNEL_SOURCES = ("pw_types.hpp", "pw_stencil.hpp", "pw_kernels.hpp", "pw_plan.hpp", "pw_advect.hip")
+
+
 def kernel_sources_sha256() -> str:
-    """sha256 over the HIP sources and the C header (identifies a kernel build)."""
+    """sha256 over the sources of the single-domain kernels (identifies a kernel build)."""
     import hashlib
     import os
-    here = os.path.dirname(os.path.abspath(__file__))
-    files = sorted(os.path.join(here, "csrc", f) for f in os.listdir(os.path.join(here, "csrc"))
-                   if f.endswith((".hip", ".hpp", ".h")))
-    files.append(os.path.join(os.path.dirname(here), "include", "pw_advect.h"))
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
     h = hashlib.sha256()
-    for p in files:
-        h.update(os.path.basename(p).encode())
-        with open(p, "rb") as f:
+    for name in KERNEL_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(here, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
