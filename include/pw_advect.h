@@ -218,8 +218,9 @@ int32_t pw_fill_halo_batched(const pw_plan *plan, int32_t ndomains,
                              const pw_domain_args *d_args, void *stream);
 
 /* Add amplitude * r to every interior point of u and v of every domain, with
-   r uniform in [-1, 1) from a counter-based hash (SplitMix64) of (seed,
-   *d_call, domain, point); then increment *d_call on the device.  Used to
+   r uniform in [-1, 1) from a counter-based hash of (seed, *d_call, domain,
+   point) -- a SplitMix64 key per (seed, call, domain), then one 32-bit
+   lowbias32 hash per element; then increment *d_call on the device.  Used to
    change the fields between repeated timestep calls, also inside a replayed
    graph.  d_call: device pointer to one 64-bit counter owned by the caller.
    Halos are not refreshed (call pw_fill_halo_batched after). */

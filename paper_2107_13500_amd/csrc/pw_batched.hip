@@ -148,9 +148,22 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
     return x ^ (x >> 31);
 }
 
+// 32-bit integer hash "lowbias32" (C. Wellons, "Prospecting for Hash
+// Functions", 2018).
+__device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
 // u += amp * r, v += amp * r' on the interior, r uniform in [-1, 1) from a
 // counter-based hash of (seed, call, domain, field, point); `call` is read
 // from device memory so a captured graph perturbs differently on each replay.
+// The (seed, call, domain) key is mixed once by SplitMix64; each element then
+// costs one 32-bit hash.
 template <typename ST>
 __global__ __launch_bounds__(256) void pw_perturb_kernel(const BatchDomain* __restrict__ table,
                                                          const pw_domain_args* __restrict__ args, uint64_t seed,
@@ -160,24 +173,26 @@ __global__ __launch_bounds__(256) void pw_perturb_kernel(const BatchDomain* __re
     const BatchDomain b = table[dom];
     const pw_domain_args& a = args[dom];
     if (!shape_matches(a.shape, b)) return;
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t npts = (int64_t)b.nx * b.ny * b.nz;
+    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+    const uint32_t npts = (uint32_t)b.nx * (uint32_t)b.ny * (uint32_t)b.nz;   // < 2^31 (checked at plan time)
     if (g >= npts) return;
-    const int k = (int)(g % b.nz);
-    const int64_t col = g / b.nz;
-    const int j = (int)(col % b.ny) + 1;
-    const int i = (int)(col / b.ny) + 1;
+    const uint32_t nz = (uint32_t)b.nz, ny = (uint32_t)b.ny;
+    const uint32_t k = g % nz;
+    const uint32_t col = g / nz;
+    const uint32_t j = col % ny + 1;
+    const uint32_t i = col / ny + 1;
     const int64_t o = k + (int64_t)j * b.sy + (int64_t)i * b.sx;
-    const uint64_t key = splitmix64(seed ^ splitmix64((uint64_t)(*call) * 0x100000001b3ull + (uint64_t)dom));
+    const uint64_t key64 = splitmix64(seed ^ splitmix64((uint64_t)(*call) * 0x100000001b3ull + (uint64_t)dom));
+    const uint32_t key = (uint32_t)key64 ^ (uint32_t)(key64 >> 32);
     ST* f[2] = {(ST*)a.u, (ST*)a.v};
     const float sc[2] = {is16<ST>::value ? scale_or_one(a.scales.in_scale[0]) : 1.0f,
                          is16<ST>::value ? scale_or_one(a.scales.in_scale[1]) : 1.0f};
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        const uint64_t h = splitmix64(key + (uint64_t)(2 * g + q));
-        const double r = (double)(h >> 11) * 0x1.0p-52 - 1.0;   // [-1, 1)
+        const uint32_t h = lowbias32(key ^ lowbias32(2u * g + (uint32_t)q));
+        const float r = (float)(h >> 8) * 0x1.0p-23f - 1.0f;   // [-1, 1)
         CT x = to_compute(f[q][o]);
-        x += static_cast<CT>(amp * r) * static_cast<CT>(sc[q]);
+        x += static_cast<CT>(amp * (double)r) * static_cast<CT>(sc[q]);
         f[q][o] = from_compute<ST>(x);
     }
 }
@@ -261,6 +276,7 @@ int32_t batched_plan_init(pw_plan* p) {
     BatchState& B = p->batch;
     for (const pw_shape& s : p->shapes) {
         if (!march_possible(s)) return PW_OK;   // batched entry points will report PW_ERR_UNSUPPORTED
+        if ((int64_t)s.nx * s.ny * s.nz >= (int64_t(1) << 31)) return PW_OK;
     }
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(nullptr, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return PW_ERR_CAPTURE;

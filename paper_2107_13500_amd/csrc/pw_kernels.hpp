@@ -367,12 +367,14 @@ struct MarchTile {
                                    hx[2], hy[2], zc[q][4], zc[q][5]};
             if constexpr (PAIR) {
                 const int l0 = li[q & ~1];   // the pair's first (even) index
+                // the pair's first level is odd (k = 1 possible, never the
+                // top); the second is even (never k = 1, the top possible)
                 if (q % 2 == 0) {
                     PairAcc<CT, NZ, WPAD, 0> A{lds + sm * se + l0, lds + sc * se + l0, lds + sp * se + l0};
-                    pw_point<AR, false>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2]);
+                    pw_point<AR, false, true, false>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2]);
                 } else {
                     PairAcc<CT, NZ, WPAD, 1> A{lds + sm * se + l0, lds + sc * se + l0, lds + sp * se + l0};
-                    pw_point<AR, false>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2]);
+                    pw_point<AR, false, false, true>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2]);
                 }
             } else {
                 LdsAcc<CT, NZ, WPAD> A{lds + sm * se + l, lds + sc * se + l, lds + sp * se + l, nz_rt, wpad()};

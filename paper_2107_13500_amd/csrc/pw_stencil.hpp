@@ -133,8 +133,11 @@ struct PointCoefs {
 // windows, where every such read stays inside the staged window): all reads
 // are issued unconditionally and the column-top and k = 1 results are picked
 // by selects, so the code is straight-line and two points of one thread can
-// share their reads.
-template <typename AR, bool GUARDED, typename Acc, typename CT = typename AR::T>
+// share their reads.  MAY_BOTTOM / MAY_TOP = false state that k is never 1 /
+// never nz for this point (known at compile time for pairs of levels in
+// even-height columns), which drops the corresponding select.
+template <typename AR, bool GUARDED, bool MAY_BOTTOM = true, bool MAY_TOP = true, typename Acc,
+          typename CT = typename AR::T>
 __device__ __forceinline__ void pw_point(const Acc& A, int k, int nz, const PointCoefs<CT>& c, CT& su, CT& sv,
                                          CT& sw) {
     if constexpr (GUARDED) {
@@ -195,14 +198,25 @@ __device__ __forceinline__ void pw_point(const Acc& A, int k, int nz, const Poin
             sw = CT(0);
         }
     } else {
-        CT fa, fb, fr, ta, tb;
+        CT fa, fb, fr;
         full(fa, fb, fr);
-        top(ta, tb);
-        const bool in = k < nz;
-        const bool live = k >= 2;
-        su = live ? (in ? fa : ta) : CT(0);
-        sv = live ? (in ? fb : tb) : CT(0);
-        sw = (live && in) ? fr : CT(0);
+        if constexpr (MAY_TOP) {
+            CT ta, tb;
+            top(ta, tb);
+            const bool in = k < nz;
+            fa = in ? fa : ta;
+            fb = in ? fb : tb;
+            fr = in ? fr : CT(0);
+        }
+        if constexpr (MAY_BOTTOM) {
+            const bool live = k >= 2;
+            fa = live ? fa : CT(0);
+            fb = live ? fb : CT(0);
+            fr = live ? fr : CT(0);
+        }
+        su = fa;
+        sv = fb;
+        sw = fr;
     }
 }
 
