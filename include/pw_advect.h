@@ -36,8 +36,9 @@
  * first (exact when they are within a factor of two); the 16-bit types, whose
  * pairwise sums are exact in FP32, use Kahan's fused multiply-add product
  * difference.  The vertical coefficients stay FP64 in memory and are rounded
- * to FP32 once per thread.  For the 16-bit types each field has a
- * power-of-two scale: stored = value * scale.
+ * to FP32 once per thread.  PW_I32 stores 32-bit fixed point and computes in
+ * FP64 (every int32 converts exactly).  For the 16-bit types and PW_I32 each
+ * field has a power-of-two scale: stored = value * scale.
  *
  * Conventions for every entry point:
  *  - Pointers named "device" are HIP device (or managed) pointers owned by
@@ -74,10 +75,11 @@ enum {
     PW_ERR_PLAN_MISMATCH = -8  /* the arguments do not match the plan */
 };
 
-/* Storage types of the six field arrays.  PW_I16 is 16-bit fixed point: a
-   signed integer with a per-field power-of-two scale (stored = value * scale,
-   rounded to nearest even and saturated to [-32768, 32767] on output). */
-enum { PW_F64 = 0, PW_F32 = 1, PW_BF16 = 2, PW_F16 = 3, PW_I16 = 4 };
+/* Storage types of the six field arrays.  PW_I16 and PW_I32 are 16- and
+   32-bit fixed point: a signed integer with a per-field power-of-two scale
+   (stored = value * scale, rounded to nearest even and saturated to the
+   type's range on output; a NaN result stores the most negative value). */
+enum { PW_F64 = 0, PW_F32 = 1, PW_BF16 = 2, PW_F16 = 3, PW_I16 = 4, PW_I32 = 5 };
 
 /* Kernel variants (pw_tuning.variant). */
 enum {
@@ -111,9 +113,9 @@ typedef struct pw_tuning {
     int32_t wg_per_cu;
 } pw_tuning;
 
-/* Per-field power-of-two scales for 16-bit storage (stored = value * scale):
-   in_scale for u, v, w and out_scale for su, sv, sw.  Ignored for PW_F64;
-   NULL means all 1. */
+/* Per-field power-of-two scales for the 16-bit types and PW_I32 (stored =
+   value * scale): in_scale for u, v, w and out_scale for su, sv, sw.  Ignored
+   for PW_F64 and PW_F32; NULL means all 1. */
 typedef struct pw_scales {
     float in_scale[3];
     float out_scale[3];
@@ -189,7 +191,7 @@ int32_t pw_advect(const pw_plan *plan,
    (the kernel reads it); its shapes must equal, in order, the shapes the plan
    was created with (checked on the device: a mismatching domain, or one with
    a NULL field pointer, is skipped and counted, see pw_plan_error_count).
-   For 16-bit storage a scale of 0 means 1. */
+   For scaled storage types a scale of 0 means 1. */
 typedef struct pw_domain_args {
     pw_shape shape;
     const void *u, *v, *w;

@@ -54,10 +54,8 @@ class DeviceBatch:
             views = [self.pool[o:o + n * esize].view(dt).view(p.nx + 2, p.ny + 2, p.nz) for o in offs[d]]
             if scales is not None:
                 sc = scales[d]
-            elif storage in (B.F16, B.I16):
-                sc = B.make_scales(inputs.fp16_input_scales(p), inputs.fp16_output_scales(p))
             else:
-                sc = B.make_scales()
+                sc = B.make_scales(*inputs.storage_scales(p, B.DTYPE_NAMES[storage]))
             for f, a in enumerate((p.u, p.v, p.w)):
                 views[f].copy_(B.to_storage(a, storage, float(sc.in_scale[f]), self.device))
             tz = [self.coef_pool[ci + q * p.nz: ci + (q + 1) * p.nz] for q in range(4)]

@@ -20,10 +20,11 @@ STATUS_NAMES = {
     -4: "PW_ERR_ALIGNMENT", -5: "PW_ERR_OUT_OF_MEMORY", -6: "PW_ERR_HIP", -7: "PW_ERR_CAPTURE",
     -8: "PW_ERR_PLAN_MISMATCH",
 }
-F64, F32, BF16, F16, I16 = 0, 1, 2, 3, 4
-SCALED = (BF16, F16, I16)
+F64, F32, BF16, F16, I16, I32 = 0, 1, 2, 3, 4, 5
+SCALED = (BF16, F16, I16, I32)
+FIXED_RANGE = {I16: (-32768, 32767), I32: (-2147483648, 2147483647)}
 VARIANT_AUTO, VARIANT_DIRECT, VARIANT_MARCH = 0, 1, 2
-DTYPE_NAMES = {F64: "f64", F32: "f32", BF16: "bf16", F16: "f16", I16: "i16"}
+DTYPE_NAMES = {F64: "f64", F32: "f32", BF16: "bf16", F16: "f16", I16: "i16", I32: "i32"}
 
 
 class PwShape(ctypes.Structure):
@@ -130,7 +131,8 @@ def _torch():
 
 def storage_of(dtype) -> int:
     torch = _torch()
-    table = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16, torch.int16: I16}
+    table = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16, torch.int16: I16,
+             torch.int32: I32}
     if dtype not in table:
         raise TypeError("unsupported field dtype %s" % dtype)
     return table[dtype]
@@ -139,20 +141,20 @@ def storage_of(dtype) -> int:
 def torch_dtype(storage: int):
     torch = _torch()
     return {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16, F16: torch.float16,
-            I16: torch.int16}[storage]
+            I16: torch.int16, I32: torch.int32}[storage]
 
 
 def to_storage(a, storage: int, scale: float = 1.0, device=None):
-    """Host float64 numpy array -> tensor of the storage type (scaled; int16
-    rounded to nearest and saturated), optionally moved to `device`."""
+    """Host float64 numpy array -> tensor of the storage type (scaled; fixed
+    point rounded to nearest even and saturated), optionally moved to `device`."""
     torch = _torch()
     t = torch.from_numpy(a)
     if device is not None:
         t = t.to(device)
     if storage in SCALED and scale != 1.0:
         t = t * scale
-    if storage == I16:
-        t = torch.round(t).clamp_(-32768, 32767)
+    if storage in FIXED_RANGE:
+        t = torch.round(t).clamp_(*FIXED_RANGE[storage])
     return t.to(torch_dtype(storage))
 
 

@@ -30,7 +30,8 @@ namespace pw {
 int64_t elem_bytes(int32_t storage) {
     switch (storage) {
         case PW_F64: return 8;
-        case PW_F32: return 4;
+        case PW_F32:
+        case PW_I32: return 4;
         case PW_BF16:
         case PW_F16:
         case PW_I16: return 2;
@@ -38,9 +39,17 @@ int64_t elem_bytes(int32_t storage) {
     }
 }
 
-int64_t compute_bytes(int32_t storage) { return storage == PW_F64 ? 8 : 4; }
+int64_t compute_bytes(int32_t storage) { return storage == PW_F64 || storage == PW_I32 ? 8 : 4; }
 
-bool scaled_storage(int32_t storage) { return storage == PW_BF16 || storage == PW_F16 || storage == PW_I16; }
+// LDS of one march workgroup: three fields per ring slot (march_slots<CT>()).
+int64_t march_lds_bytes(int32_t storage, int32_t wpad) {
+    const int64_t slots = compute_bytes(storage) == 8 ? march_slots<double>() : march_slots<float>();
+    return 3 * slots * (int64_t)wpad * compute_bytes(storage);
+}
+
+bool scaled_storage(int32_t storage) {
+    return storage == PW_BF16 || storage == PW_F16 || storage == PW_I16 || storage == PW_I32;
+}
 
 int32_t normalize_shape(const pw_shape& in, pw_shape* out) {
     pw_shape s = in;
@@ -93,7 +102,7 @@ int32_t resolve_launch(int32_t storage, const pw_shape& s, const pw_tuning& t, L
         r.seg = t.seg ? std::min(t.seg, s.nx) : auto_seg(s, r.nchunks);
         r.nseg = (s.nx + r.seg - 1) / r.seg;
         r.wpad = ((chunk + 2 * s.nz) + 3) / 4 * 4;
-        r.lds_bytes = 9 * (int64_t)r.wpad * compute_bytes(storage);
+        r.lds_bytes = march_lds_bytes(storage, r.wpad);
         r.workgroups = (int64_t)r.nchunks * r.nseg;
         if (r.workgroups >= (int64_t(1) << 31)) return PW_ERR_INVALID_ARG;
     } else {
@@ -179,6 +188,7 @@ hipError_t launch_domain(int32_t storage, const DomainArgs& d, const Launch& L, 
         case PW_BF16: return launch_typed<bf16_t>(d, L, vec, stream);
         case PW_F16: return launch_typed<f16_t>(d, L, vec, stream);
         case PW_I16: return launch_typed<fx16_t>(d, L, vec, stream);
+        case PW_I32: return launch_typed<fx32_t>(d, L, vec, stream);
         default: return hipErrorInvalidValue;
     }
 }

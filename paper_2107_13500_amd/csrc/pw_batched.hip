@@ -44,8 +44,8 @@ __device__ __forceinline__ DomainArgs domain_from(const pw_domain_args& a, const
     d.tzd2 = a.tzd2;
     float in_s[3], out_s[3];
     for (int f = 0; f < 3; ++f) {
-        in_s[f] = is16<ST>::value ? scale_or_one(a.scales.in_scale[f]) : 1.0f;
-        out_s[f] = is16<ST>::value ? scale_or_one(a.scales.out_scale[f]) : 1.0f;
+        in_s[f] = scaled_type<ST>::value ? scale_or_one(a.scales.in_scale[f]) : 1.0f;
+        out_s[f] = scaled_type<ST>::value ? scale_or_one(a.scales.out_scale[f]) : 1.0f;
     }
     fold_coefficients(a.tcx, a.tcy, in_s, out_s, d.cx, d.cy, d.cz);
     d.nx = b.nx;
@@ -185,8 +185,8 @@ __global__ __launch_bounds__(256) void pw_perturb_kernel(const BatchDomain* __re
     const uint64_t key64 = splitmix64(seed ^ splitmix64((uint64_t)(*call) * 0x100000001b3ull + (uint64_t)dom));
     const uint32_t key = (uint32_t)key64 ^ (uint32_t)(key64 >> 32);
     ST* f[2] = {(ST*)a.u, (ST*)a.v};
-    const float sc[2] = {is16<ST>::value ? scale_or_one(a.scales.in_scale[0]) : 1.0f,
-                         is16<ST>::value ? scale_or_one(a.scales.in_scale[1]) : 1.0f};
+    const float sc[2] = {scaled_type<ST>::value ? scale_or_one(a.scales.in_scale[0]) : 1.0f,
+                         scaled_type<ST>::value ? scale_or_one(a.scales.in_scale[1]) : 1.0f};
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const uint32_t h = lowbias32(key ^ lowbias32(2u * g + (uint32_t)q));
@@ -244,6 +244,7 @@ int batched_occupancy(int32_t storage, int32_t chunk, int64_t lds_bytes) {
         case PW_BF16: return occupancy_typed<bf16_t>(chunk, lds_bytes);
         case PW_F16: return occupancy_typed<f16_t>(chunk, lds_bytes);
         case PW_I16: return occupancy_typed<fx16_t>(chunk, lds_bytes);
+        case PW_I32: return occupancy_typed<fx32_t>(chunk, lds_bytes);
         default: return 0;
     }
 }
@@ -318,7 +319,7 @@ int32_t batched_plan_init(pw_plan* p) {
     L.seg = seg_used;
     L.block = 256;
     L.wpad = ((chunk + 2 * nzmax) + 3) / 4 * 4;
-    L.lds_bytes = 9 * (int64_t)L.wpad * compute_bytes(p->storage);
+    L.lds_bytes = march_lds_bytes(p->storage, L.wpad);
     L.tiles = tiles;
 
     int dev = 0;
@@ -385,6 +386,7 @@ int32_t pw_advect_batched(const pw_plan* plan, int32_t ndomains, const pw_domain
         case PW_BF16: e = dispatch_batched<bf16_t>(plan, d_args, s); break;
         case PW_F16: e = dispatch_batched<f16_t>(plan, d_args, s); break;
         case PW_I16: e = dispatch_batched<fx16_t>(plan, d_args, s); break;
+        case PW_I32: e = dispatch_batched<fx32_t>(plan, d_args, s); break;
         default: return PW_ERR_UNSUPPORTED;
     }
     if (e != hipSuccess) return report_hip(e);
@@ -405,6 +407,7 @@ int32_t pw_fill_halo_batched(const pw_plan* plan, int32_t ndomains, const pw_dom
         case PW_BF16: hipLaunchKernelGGL(pw_halo_kernel<bf16_t>, grid, dim3(256), 0, s, tb, d_args); break;
         case PW_F16: hipLaunchKernelGGL(pw_halo_kernel<f16_t>, grid, dim3(256), 0, s, tb, d_args); break;
         case PW_I16: hipLaunchKernelGGL(pw_halo_kernel<fx16_t>, grid, dim3(256), 0, s, tb, d_args); break;
+        case PW_I32: hipLaunchKernelGGL(pw_halo_kernel<fx32_t>, grid, dim3(256), 0, s, tb, d_args); break;
         default: return PW_ERR_UNSUPPORTED;
     }
     hipError_t e = hipGetLastError();
@@ -436,6 +439,9 @@ int32_t pw_perturb_batched(const pw_plan* plan, int32_t ndomains, const pw_domai
             break;
         case PW_I16:
             hipLaunchKernelGGL(pw_perturb_kernel<fx16_t>, grid, dim3(256), 0, s, tb, d_args, seed, d_call, amplitude);
+            break;
+        case PW_I32:
+            hipLaunchKernelGGL(pw_perturb_kernel<fx32_t>, grid, dim3(256), 0, s, tb, d_args, seed, d_call, amplitude);
             break;
         default: return PW_ERR_UNSUPPORTED;
     }

@@ -55,10 +55,12 @@ struct MarchGeom {
     int32_t wpad;      // LDS elements per field per slot
 };
 
-template <typename ST> struct is16 { static constexpr bool value = false; };
-template <> struct is16<bf16_t> { static constexpr bool value = true; };
-template <> struct is16<f16_t> { static constexpr bool value = true; };
-template <> struct is16<fx16_t> { static constexpr bool value = true; };
+// Storage types that carry per-field power-of-two scales.
+template <typename ST> struct scaled_type { static constexpr bool value = false; };
+template <> struct scaled_type<bf16_t> { static constexpr bool value = true; };
+template <> struct scaled_type<f16_t> { static constexpr bool value = true; };
+template <> struct scaled_type<fx16_t> { static constexpr bool value = true; };
+template <> struct scaled_type<fx32_t> { static constexpr bool value = true; };
 
 // Folded coefficients (see DomainArgs) from tcx, tcy and the storage scales.
 __host__ __device__ inline void fold_coefficients(double tcx, double tcy, const float in_scale[3],
@@ -81,20 +83,35 @@ __device__ __forceinline__ void store_out(ST* p, typename compute_of<ST>::type x
         uint16_t bits;
         __builtin_memcpy(&bits, &y, 2);
         __builtin_nontemporal_store(bits, reinterpret_cast<uint16_t*>(p));
+    } else if constexpr (std::is_same<ST, fx32_t>::value) {
+        __builtin_nontemporal_store(y.v, reinterpret_cast<int32_t*>(p));
     } else {
         __builtin_nontemporal_store(y, p);
     }
 }
 
 // Two consecutive outputs p[0], p[1] with one store (p aligned to 2 elements).
+// BF16 and FP16 pairs are rounded by one packed conversion (v_cvt_pk_bf16_f32,
+// v_cvt_pk_f16_f32: round to nearest even, as from_compute).
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 template <typename ST>
 __device__ __forceinline__ void store_pair(ST* p, typename compute_of<ST>::type a, typename compute_of<ST>::type b) {
     if constexpr (std::is_same<ST, double>::value) {
         __builtin_nontemporal_store(f64x2{a, b}, reinterpret_cast<f64x2*>(p));
     } else if constexpr (std::is_same<ST, float>::value) {
         __builtin_nontemporal_store(f32x2{a, b}, reinterpret_cast<f32x2*>(p));
+    } else if constexpr (std::is_same<ST, fx32_t>::value) {
+        typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+        __builtin_nontemporal_store(i32x2{from_compute<ST>(a).v, from_compute<ST>(b).v}, reinterpret_cast<i32x2*>(p));
+    } else if constexpr (std::is_same<ST, bf16_t>::value || std::is_same<ST, f16_t>::value) {
+        using H2 = typename std::conditional<std::is_same<ST, bf16_t>::value, bf16x2, f16x2>::type;
+        const H2 h = __builtin_convertvector(f32x2{a, b}, H2);
+        uint32_t bits;
+        __builtin_memcpy(&bits, &h, 4);
+        __builtin_nontemporal_store(bits, reinterpret_cast<uint32_t*>(p));
     } else {
         ST ya = from_compute<ST>(a), yb = from_compute<ST>(b);
         uint16_t ba, bb;
@@ -219,18 +236,19 @@ template <> struct vec2_of<float> { using type = f32x2; };
 // shared.
 template <typename CT, int NZ, int WPAD, int O>
 struct PairAcc {
-    const CT* m;   // plane i-1 at the pair's (even) window index
-    const CT* c;   // plane i
-    const CT* p;   // plane i+1
-    template <int di> __device__ __forceinline__ const CT* sel() const {
-        return di < 0 ? m : (di > 0 ? p : c);
+    // field F of plane i-1, i, i+1 at the pair's (even) window index
+    const CT* m[3];
+    const CT* c[3];
+    const CT* p[3];
+    template <int F, int di> __device__ __forceinline__ const CT* sel() const {
+        return di < 0 ? m[F] : (di > 0 ? p[F] : c[F]);
     }
     template <int F, int dk, int dj, int di>
     __device__ __forceinline__ CT get() const {
         constexpr int e = O + dk;                              // -1 .. 2 from the pair start
         constexpr int start = e < 0 ? -2 : (e >= 2 ? 2 : 0);   // aligned two-element block
         using V2 = typename vec2_of<CT>::type;
-        const V2 val = *reinterpret_cast<const V2*>(sel<di>() + F * WPAD + dj * NZ + start);
+        const V2 val = *reinterpret_cast<const V2*>(sel<F, di>() + dj * NZ + start);
         return val[e - start];
     }
     template <int dk, int dj, int di> __device__ __forceinline__ CT u() const { return get<0, dk, dj, di>(); }
@@ -238,9 +256,14 @@ struct PairAcc {
     template <int dk, int dj, int di> __device__ __forceinline__ CT w() const { return get<2, dk, dj, di>(); }
 };
 
+// Planes held in the LDS ring: four for FP32 compute (one barrier per plane),
+// three for FP64, whose larger slots would otherwise cost occupancy.
+template <typename CT> constexpr int march_slots() { return sizeof(CT) == 4 ? 4 : 3; }
+
 // One (chunk, segment) tile of the march: chunk c of the interior (j, k) run,
 // planes i_begin .. i_end.  Every thread of the workgroup must run it (it
-// holds barriers); `lds` must hold 9 * wpad compute-type elements.
+// holds barriers); `lds` must hold 3 * march_slots<CT>() * wpad compute-type
+// elements.
 // NZ > 0: the domain's nz equals NZ and wpad equals round_up4(P + 2 NZ).
 template <typename ST, int NT, int P, bool VEC, int NZ>
 struct MarchTile {
@@ -251,6 +274,7 @@ struct MarchTile {
     static constexpr int PPT = P / NT;                                     // points per thread
     static constexpr bool PAIR = VEC && NZ > 0 && NZ % 2 == 0 && P % (2 * NT) == 0;
     static constexpr int WPAD = NZ > 0 ? round_up4(P + 2 * NZ) : 0;
+    static constexpr int NSLOT = march_slots<CT>();                       // planes in the LDS ring
     using Raw = typename std::conditional<VEC, uint4, ST>::type;
     static_assert(P % NT == 0, "P must be a multiple of the block size");
 
@@ -264,9 +288,16 @@ struct MarchTile {
     CT zc[PPT][6];         // per-level vertical coefficients of each point
     // The window vectors of all three fields are spread over the workgroup:
     // round r of this thread moves vector t + r NT -- field fsel[r] (-1: none),
-    // element offset goff[r] within the plane window, LDS offset loff[r].
+    // element pointer gptr[r] into the plane-0 window, LDS offset loff[r].
+    // FP32 compute with pairs: LDS element offset of each (slot, field) at
+    // each pair's window index.  They are made opaque to the compiler once, so
+    // it keeps them in registers instead of re-deriving a base for every
+    // merged two-address LDS read (each re-derivation is one VALU add per
+    // plane).  FP64 pairs are single 16-byte reads with immediate offsets.
+    static constexpr bool BASES = PAIR && sizeof(CT) == 4;
+    int pbo[BASES ? PPT / 2 : 1][3 * NSLOT];
     int fsel[NVR];
-    int goff[NVR];
+    const char* gptr[NVR];   // field base + window offset; plane ip adds ip * sx elements
     int loff[NVR];
     Raw st[NVR];
 
@@ -288,7 +319,8 @@ struct MarchTile {
             const int f = v < 3 * nvec ? v / nvec : -1;
             const int q = (v - (f < 0 ? 0 : f) * nvec) * VW;
             fsel[r] = f;
-            goff[r] = wb + q;
+            const ST* base = static_cast<const ST*>(f == 0 ? d.u : (f == 1 ? d.v : d.w));
+            gptr[r] = reinterpret_cast<const char*>(base + (wb + q));
             loff[r] = (f < 0 ? 0 : f) * wpad() + q;
         }
 #pragma unroll
@@ -311,18 +343,25 @@ struct MarchTile {
             hx[f] = static_cast<CT>(d.cx[f]);
             hy[f] = static_cast<CT>(d.cy[f]);
         }
+        if constexpr (BASES) {
+#pragma unroll
+            for (int q = 0; q < PPT / 2; ++q) {
+#pragma unroll
+                for (int n = 0; n < 3 * NSLOT; ++n) {
+                    int o = (n / 3) * slot_elems() + (n % 3) * wpad() + li[2 * q];
+                    asm volatile("" : "+v"(o));
+                    pbo[q][n] = o;
+                }
+            }
+        }
     }
 
     // Issue the global loads of the window of plane ip.
     __device__ __forceinline__ void load(int64_t ip) {
-        const int64_t po = ip * d.sx;
+        const int64_t po = ip * d.sx * (int64_t)sizeof(ST);   // uniform byte offset of the plane
 #pragma unroll
         for (int r = 0; r < NVR; ++r) {
-            const int f = fsel[r];
-            if (f >= 0) {
-                const ST* base = static_cast<const ST*>(f == 0 ? d.u : (f == 1 ? d.v : d.w));
-                st[r] = *reinterpret_cast<const Raw*>(base + po + goff[r]);
-            }
+            if (fsel[r] >= 0) st[r] = *reinterpret_cast<const Raw*>(gptr[r] + po);
         }
     }
 
@@ -366,14 +405,28 @@ struct MarchTile {
             const PointCoefs<CT> c{hx[0], hy[0], zc[q][0], zc[q][1], hy[1], hx[1], zc[q][2], zc[q][3],
                                    hx[2], hy[2], zc[q][4], zc[q][5]};
             if constexpr (PAIR) {
-                const int l0 = li[q & ~1];   // the pair's first (even) index
+                const CT *m[3], *cc[3], *pp[3];
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    if constexpr (BASES) {
+                        const int* b = pbo[q / 2];
+                        m[f] = lds + b[sm * 3 + f];
+                        cc[f] = lds + b[sc * 3 + f];
+                        pp[f] = lds + b[sp * 3 + f];
+                    } else {
+                        const int l0 = li[q & ~1];   // the pair's first (even) index
+                        m[f] = lds + sm * se + f * WPAD + l0;
+                        cc[f] = lds + sc * se + f * WPAD + l0;
+                        pp[f] = lds + sp * se + f * WPAD + l0;
+                    }
+                }
                 // the pair's first level is odd (k = 1 possible, never the
                 // top); the second is even (never k = 1, the top possible)
                 if (q % 2 == 0) {
-                    PairAcc<CT, NZ, WPAD, 0> A{lds + sm * se + l0, lds + sc * se + l0, lds + sp * se + l0};
+                    PairAcc<CT, NZ, WPAD, 0> A{{m[0], m[1], m[2]}, {cc[0], cc[1], cc[2]}, {pp[0], pp[1], pp[2]}};
                     pw_point<AR, false, true, false>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2]);
                 } else {
-                    PairAcc<CT, NZ, WPAD, 1> A{lds + sm * se + l0, lds + sc * se + l0, lds + sp * se + l0};
+                    PairAcc<CT, NZ, WPAD, 1> A{{m[0], m[1], m[2]}, {cc[0], cc[1], cc[2]}, {pp[0], pp[1], pp[2]}};
                     pw_point<AR, false, false, true>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2]);
                 }
             } else {
@@ -400,12 +453,16 @@ struct MarchTile {
     }
 
     // One march step: publish plane i+1, prefetch plane i+2, compute plane i.
+    // With three slots the slot of plane i-1 is refilled by the next step, so
+    // a second barrier keeps it until every wave has computed plane i; with
+    // four slots that refill happens one step later, behind the next step's
+    // barrier, and one barrier per plane suffices.
     __device__ __forceinline__ void step(int i, int i_end, int sm, int sc, int sp) {
         put(sp);
         __syncthreads();
         if (i + 2 <= i_end + 1) load((int64_t)(i + 2));
         compute(i, sm, sc, sp);
-        __syncthreads();
+        if constexpr (NSLOT == 3) __syncthreads();
     }
 
     __device__ __forceinline__ void run(int i_begin, int i_end) {
@@ -414,7 +471,7 @@ struct MarchTile {
         load((int64_t)i_begin);
         put(1);
         load((int64_t)(i_begin + 1));
-        if constexpr (NZ > 0) {
+        if constexpr (NZ > 0 && NSLOT == 3) {
             // ring rotation unrolled: every slot offset is a compile-time constant
             for (int i = i_begin; i <= i_end; i += 3) {
                 step(i, i_end, 0, 1, 2);
@@ -423,16 +480,27 @@ struct MarchTile {
                 if (i + 2 > i_end) break;
                 step(i + 2, i_end, 2, 0, 1);
             }
+        } else if constexpr (NZ > 0) {
+            for (int i = i_begin; i <= i_end; i += 4) {
+                step(i, i_end, 0, 1, 2);
+                if (i + 1 > i_end) break;
+                step(i + 1, i_end, 1, 2, 3);
+                if (i + 2 > i_end) break;
+                step(i + 2, i_end, 2, 3, 0);
+                if (i + 3 > i_end) break;
+                step(i + 3, i_end, 3, 0, 1);
+            }
         } else {
             int sm = 0, sc = 1, sp = 2;
             for (int i = i_begin; i <= i_end; ++i) {
                 step(i, i_end, sm, sc, sp);
-                const int t = sm;
                 sm = sc;
                 sc = sp;
-                sp = t;
+                sp = sp + 1 == NSLOT ? 0 : sp + 1;
             }
         }
+        // the next tile of a persistent workgroup refills slots 0 and 1
+        if constexpr (NSLOT == 4) __syncthreads();
     }
 };
 

@@ -14,7 +14,8 @@
 //   vert   c1 a (w1 + w2) - c2 c (w3 + w4)   vertical, per-level coefficients
 //   vself  d1 m (w + m) - d2 p (w + p)       w along z
 // Three arithmetic policies evaluate them:
-//   ArithF64    FP64, exactly as written (Listing 1's order).
+//   ArithF64    FP64, exactly as written (Listing 1's order); also for 32-bit
+//               fixed-point storage.
 //   ArithSplit  FP32 storage, FP32 compute: algebraically identical
 //               difference-first forms -- neighbouring values are subtracted
 //               first, which is exact when they are within a factor of two of
@@ -41,6 +42,7 @@ namespace pw {
 // ---------------------------------------------------------------- FP64: as written
 struct ArithF64 {
     using T = double;
+    static constexpr bool kExactZeroFlux = true;   // c2 * 0 * (w3 + w4) leaves the sum unchanged
     static __device__ __forceinline__ double self_flux(double A, double U, double C) {
         return A * (U + A) - C * (U + C);
     }
@@ -60,6 +62,8 @@ struct ArithF64 {
 // ---------------------------------------------------------------- FP32: difference first
 struct ArithSplit {
     using T = float;
+    // the difference-first vertical form still rounds w3 + w4 when c = 0
+    static constexpr bool kExactZeroFlux = false;
     // A (U + A) - C (U + C) = (A - C) (U + A + C)
     static __device__ __forceinline__ float self_flux(float A, float U, float C) { return (A - C) * ((U + A) + C); }
     // E F - G H = ((E - G)(F + H) + (E + G)(F - H)) / 2, with F - H = (v1 - v3) + (v2 - v4)
@@ -92,6 +96,7 @@ struct ArithSplit {
 // ---------------------------------------------------------------- FP32: Kahan product differences
 struct ArithKahan {
     using T = float;
+    static constexpr bool kExactZeroFlux = true;   // a b - 0 d = RN(a b) exactly
     // a b - c d: w = RN(c d); e = c d - w exactly; RN(RN(a b - w) - e)
     static __device__ __forceinline__ float pdiff(float a, float b, float c, float d) {
         const float w = c * d;
@@ -115,6 +120,7 @@ struct ArithKahan {
 template <typename ST> struct arith_of { using type = ArithKahan; };
 template <> struct arith_of<double> { using type = ArithF64; };
 template <> struct arith_of<float> { using type = ArithSplit; };
+template <> struct arith_of<fx32_t> { using type = ArithF64; };
 
 // Coefficients of one point.  Each output's x and y coefficients are uniform
 // over the domain; the vertical pair is per level.  For 16-bit storage the
@@ -172,17 +178,10 @@ __device__ __forceinline__ void pw_point(const Acc& A, int k, int nz, const Poin
 
     const CT w_u_lo = A.template w<-1, 0, 1>();   // w(k-1, j, i+1): lower z face of u
     const CT w_v_lo = A.template w<-1, 1, 0>();   // w(k-1, j+1, i): lower z face of v
-    // column top: the upper vertical flux of su and sv is dropped; sw = 0
-    auto top = [&](CT& a, CT& b) {
-        a = s + c.z1u * u_zm * (w_zm + w_u_lo);
-        b = t + c.z1v * v_zm * (w_zm + w_v_lo);
-    };
-    auto full = [&](CT& a, CT& b, CT& r) {
-        const CT w_xp = A.template w<0, 0, 1>();
-        const CT w_yp = A.template w<0, 1, 0>();
-        const CT u_zp = A.template u<1, 0, 0>();
-        const CT v_zp = A.template v<1, 0, 0>();
-        const CT w_zp = A.template w<1, 0, 0>();
+    const CT w_xp = A.template w<0, 0, 1>();
+    const CT w_yp = A.template w<0, 1, 0>();
+    // The three outputs given the three values above the point.
+    auto eval = [&](CT u_zp, CT v_zp, CT w_zp, CT& a, CT& b, CT& r) {
         a = AR::add_vert(s, c.z1u, u_zm, w_zm, w_u_lo, c.z2u, u_zp, w0, w_xp);
         b = AR::add_vert(t, c.z1v, v_zm, w_zm, w_v_lo, c.z2v, v_zp, w0, w_yp);
         // sw: x and y terms with u, v summed over levels k, k+1; then w along z
@@ -190,22 +189,41 @@ __device__ __forceinline__ void pw_point(const Acc& A, int k, int nz, const Poin
         q = q + c.yw * AR::cross_flux(A.template w<0, -1, 0>(), v_ym, A.template v<1, -1, 0>(), w_yp, v0, v_zp);
         r = AR::add_vself(q, c.z1w, w_zm, w0, c.z2w, w_zp);
     };
+    // column top: su and sv without their upper vertical flux (Sec. III)
+    auto top = [&](CT& a, CT& b) {
+        a = s + c.z1u * u_zm * (w_zm + w_u_lo);
+        b = t + c.z1v * v_zm * (w_zm + w_v_lo);
+    };
     if constexpr (GUARDED) {
         if (k < nz) {
-            full(su, sv, sw);
+            eval(A.template u<1, 0, 0>(), A.template v<1, 0, 0>(), A.template w<1, 0, 0>(), su, sv, sw);
         } else {
             top(su, sv);
             sw = CT(0);
         }
     } else {
+        // every read is inside the staged window (level nz + 1 of a column is
+        // level 1 of the next one)
+        CT u_zp = A.template u<1, 0, 0>();
+        CT v_zp = A.template v<1, 0, 0>();
+        const CT w_zp = A.template w<1, 0, 0>();
+        const bool in = k < nz;
+        constexpr bool kZeroTop = MAY_TOP && AR::kExactZeroFlux;
+        if constexpr (kZeroTop) {
+            // zero values above the top make the upper vertical fluxes exact
+            // zeros, which is the column-top form at no extra cost
+            u_zp = in ? u_zp : CT(0);
+            v_zp = in ? v_zp : CT(0);
+        }
         CT fa, fb, fr;
-        full(fa, fb, fr);
+        eval(u_zp, v_zp, w_zp, fa, fb, fr);
         if constexpr (MAY_TOP) {
-            CT ta, tb;
-            top(ta, tb);
-            const bool in = k < nz;
-            fa = in ? fa : ta;
-            fb = in ? fb : tb;
+            if constexpr (!kZeroTop) {
+                CT ta, tb;
+                top(ta, tb);
+                fa = in ? fa : ta;
+                fb = in ? fb : tb;
+            }
             fr = in ? fr : CT(0);
         }
         if constexpr (MAY_BOTTOM) {

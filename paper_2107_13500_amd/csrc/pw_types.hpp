@@ -7,7 +7,7 @@
 namespace pw {
 
 // bfloat16 stored as its raw 16 bits; FP16 as the compiler's _Float16;
-// 16-bit fixed point as a signed integer (value = stored / scale).
+// 16- and 32-bit fixed point as signed integers (value = stored / scale).
 struct bf16_t {
     uint16_t bits;
 };
@@ -15,12 +15,18 @@ using f16_t = _Float16;
 struct fx16_t {
     int16_t v;
 };
+struct fx32_t {
+    int32_t v;
+};
 
 // ---------------------------------------------------------------------------
 // compute type of each storage type
 // ---------------------------------------------------------------------------
+// 32-bit fixed point computes in FP64: every int32 converts exactly, and FP32
+// would drop the low 8 bits of the stored values.
 template <typename ST> struct compute_of { using type = float; };
 template <> struct compute_of<double> { using type = double; };
+template <> struct compute_of<fx32_t> { using type = double; };
 
 // ---------------------------------------------------------------------------
 // storage -> compute
@@ -29,6 +35,7 @@ __device__ __forceinline__ double to_compute(double x) { return x; }
 __device__ __forceinline__ float to_compute(float x) { return x; }
 __device__ __forceinline__ float to_compute(f16_t x) { return static_cast<float>(x); }
 __device__ __forceinline__ float to_compute(fx16_t x) { return static_cast<float>(x.v); }
+__device__ __forceinline__ double to_compute(fx32_t x) { return static_cast<double>(x.v); }
 __device__ __forceinline__ float to_compute(bf16_t x) {
     return __uint_as_float(static_cast<uint32_t>(x.bits) << 16);
 }
@@ -45,6 +52,13 @@ template <> __device__ __forceinline__ fx16_t from_compute<fx16_t>(float x) {
     const float r = __builtin_fminf(__builtin_fmaxf(__builtin_rintf(x), -32768.0f), 32767.0f);
     fx16_t y;
     y.v = static_cast<int16_t>(static_cast<int>(r));
+    return y;
+}
+// round to nearest even, saturate to the int32 range (NaN becomes -2^31)
+template <> __device__ __forceinline__ fx32_t from_compute<fx32_t>(double x) {
+    const double r = __builtin_fmin(__builtin_fmax(__builtin_rint(x), -2147483648.0), 2147483647.0);
+    fx32_t y;
+    y.v = static_cast<int32_t>(r);
     return y;
 }
 template <> __device__ __forceinline__ bf16_t from_compute<bf16_t>(float x) {

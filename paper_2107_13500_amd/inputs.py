@@ -274,9 +274,25 @@ def output_bounds(p: Problem):
     return bu, bv, bw
 
 
-def fp16_input_scales(p: Problem):
-    return tuple(pow2_scale(float(np.max(np.abs(a)))) for a in (p.u, p.v, p.w))
+def fp16_input_scales(p: Problem, target: float = 2.0 ** 14):
+    return tuple(pow2_scale(float(np.max(np.abs(a))), target) for a in (p.u, p.v, p.w))
 
 
-def fp16_output_scales(p: Problem):
-    return tuple(pow2_scale(b) for b in output_bounds(p))
+def fp16_output_scales(p: Problem, target: float = 2.0 ** 14):
+    return tuple(pow2_scale(b, target) for b in output_bounds(p))
+
+
+# Largest scaled magnitude per scaled storage type: FP16 and int16 keep values
+# below 2^14 (FP16 max 65504, int16 max 32767); int32 below 2^30.
+SCALE_TARGET = {"f16": 2.0 ** 14, "i16": 2.0 ** 14, "i32": 2.0 ** 30}
+
+
+def storage_scales(p: Problem, dtype: str):
+    """(input scales, output scales) for storage `dtype` ("f64", "f32",
+    "bf16", "f16", "i16", "i32"): powers of two from the input maxima and the
+    a-priori output bounds; all 1 where the type needs none (BF16 keeps the
+    FP32 exponent range)."""
+    if dtype not in SCALE_TARGET:
+        return (1.0, 1.0, 1.0), (1.0, 1.0, 1.0)
+    t = SCALE_TARGET[dtype]
+    return fp16_input_scales(p, t), fp16_output_scales(p, t)

@@ -16,7 +16,7 @@ FLOPS_PER_CELL = 63        # 21 per field, Sec. III
 FLOPS_COLUMN_TOP = 55      # 17 + 17 + 21, Sec. III
 BYTES_PER_POINT_F64 = 48   # 3 arrays in + 3 out, Sec. IV data volumes
 
-ELEM_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2, "i16": 2}
+ELEM_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2, "i16": 2, "i32": 4}
 
 
 def flops_per_column(nz: int) -> int:

@@ -63,7 +63,7 @@ def test_batched_f64_parity_and_bit_identity(tuning):
             assert torch.equal(a[1:-1, 1:-1], b[1:-1, 1:-1]), "domain %d differs from pw_advect" % d
 
 
-@pytest.mark.parametrize("storage", [B.F32, B.BF16, B.F16, B.I16], ids=["f32", "bf16", "f16", "i16"])
+@pytest.mark.parametrize("storage", [B.F32, B.BF16, B.F16, B.I16, B.I32], ids=["f32", "bf16", "f16", "i16", "i32"])
 def test_batched_reduced_storage_matches_single_calls(storage):
     probs = small_problems(seed=400)
     batch = BT.DeviceBatch(probs, storage, DEV)
