@@ -191,6 +191,9 @@ int32_t pw_advect(const pw_plan *plan,
    (the kernel reads it); its shapes must equal, in order, the shapes the plan
    was created with (checked on the device: a mismatching domain, or one with
    a NULL field pointer, is skipped and counted, see pw_plan_error_count).
+   When every shape of the plan allows 16-byte vector access (nz, sy and sx
+   multiples of 16 / element size), the six field pointers must also be
+   16-byte aligned; a record that is not is skipped and counted the same way.
    For scaled storage types a scale of 0 means 1. */
 typedef struct pw_domain_args {
     pw_shape shape;
@@ -231,8 +234,9 @@ int32_t pw_perturb_batched(const pw_plan *plan, int32_t ndomains,
                            unsigned long long *d_call, double amplitude, void *stream);
 
 /* Number of batched-domain records skipped so far because their shape did
-   not match the plan or a field pointer was NULL.  Synchronous (copies one
-   word from the device).  `count` is a host out-pointer. */
+   not match the plan, a field pointer was NULL or (vector-aligned plans) not
+   16-byte aligned.  Synchronous (copies one word from the device).  `count`
+   is a host out-pointer. */
 int32_t pw_plan_error_count(const pw_plan *plan, unsigned long long *count);
 
 /* Host-resident domains (paper Sec. IV: the accelerator run with the

@@ -13,6 +13,7 @@ import shutil
 import subprocess
 import sys
 import tempfile
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -45,17 +46,21 @@ def build(verbose: bool = False, extra=()) -> str:
     """Compile all sources and link ``libpwadvect.so`` (always rebuilds)."""
     cc = hipcc()
     with tempfile.TemporaryDirectory(prefix="pwadv_build_") as tmp:
-        objs = []
+        jobs = []
         for src in SOURCES:
             path = os.path.join(CSRC, src)
             if not os.path.exists(path):
                 continue
             obj = os.path.join(tmp, os.path.splitext(src)[0] + ".o")
-            cmd = [cc, *HIPCC_FLAGS, *extra, "-c", path, "-o", obj]
+            jobs.append(([cc, *HIPCC_FLAGS, *extra, "-c", path, "-o", obj], obj))
             if verbose:
-                print(" ".join(cmd), flush=True)
-            subprocess.run(cmd, check=True)
-            objs.append(obj)
+                print(" ".join(jobs[-1][0]), flush=True)
+        # one compiler process per source file, in parallel
+        workers = max(1, min(len(jobs), os.cpu_count() or 1, 8))
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            for f in [ex.submit(subprocess.run, cmd, check=True) for cmd, _ in jobs]:
+                f.result()
+        objs = [obj for _, obj in jobs]
         out_tmp = LIBRARY + ".tmp%d" % os.getpid()
         cmd = [cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", out_tmp]
         if verbose:

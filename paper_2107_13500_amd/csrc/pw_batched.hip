@@ -68,7 +68,17 @@ __device__ __forceinline__ int find_domain(const BatchDomain* table, int ndom, i
 
 __device__ __forceinline__ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-template <typename ST, int NT, int P>
+// Which per-tile code paths a batched kernel carries.  Every path inlined
+// into the persistent kernel counts towards its register allocation, so a
+// plan launches the narrowest kind its shapes allow:
+//   kFixedNz  vector loads, column heights 64 / 96 / 128 only;
+//   kVector   vector loads, any column height;
+//   kAny      also element-wise loads (shapes without vector alignment).
+// The vector kinds need every field pointer 16-byte aligned; a record that
+// is not is skipped and counted like a shape mismatch.
+enum BatchKind { kFixedNz = 0, kVector = 1, kAny = 2 };
+
+template <typename ST, int NT, int P, int KIND>
 __global__ __launch_bounds__(NT) void pw_batched_kernel(const BatchDomain* __restrict__ table, int ndom,
                                                         int64_t ntiles, const pw_domain_args* __restrict__ args,
                                                         int seg, unsigned long long* errors,
@@ -76,7 +86,18 @@ __global__ __launch_bounds__(NT) void pw_batched_kernel(const BatchDomain* __res
     using CT = typename compute_of<ST>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     CT* lds = reinterpret_cast<CT*>(smem_raw);
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    // Workgroups are dispatched round-robin over the XCDs.  Give each XCD a
+    // contiguous share of the tile range, walked by its own workgroups, so
+    // the tiles in flight on one XCD are neighbouring chunks and segments of
+    // the same domains and share their halo columns and planes in its L2.
+    const int G = (int)gridDim.x;
+    const int x = (int)blockIdx.x % kNumXcd;
+    const int slot = (int)blockIdx.x / kNumXcd;
+    const int q = G / kNumXcd, r = G % kNumXcd;
+    const int wgs = q + (x < r ? 1 : 0);                 // workgroups on this XCD
+    const int before = x * q + (x < r ? x : r);          // workgroups on lower XCDs
+    const int64_t t_end = ntiles * (before + wgs) / G;
+    for (int64_t t = ntiles * before / G + slot; t < t_end; t += wgs) {
         const int dom = find_domain(table, ndom, t);
         const BatchDomain b = table[dom];
         const int64_t local = t - b.tile_begin;
@@ -92,12 +113,18 @@ __global__ __launch_bounds__(NT) void pw_batched_kernel(const BatchDomain* __res
         const int i_end = min(i_begin + seg - 1, b.nx);
         const bool vec = vec_shapes && aligned16(a.u) && aligned16(a.v) && aligned16(a.w) && aligned16(a.su) &&
                          aligned16(a.sv) && aligned16(a.sw);
+        if (KIND != kAny && !vec) {
+            if (threadIdx.x == 0 && local == 0) atomicAdd(errors, 1ull);
+            continue;   // uniform over the workgroup
+        }
         const int wpad = round_up4(P + 2 * b.nz);
         if (vec && b.nz == 64) march_tile<ST, NT, P, true, 64>(d, c, i_begin, i_end, wpad, lds);
         else if (vec && b.nz == 96) march_tile<ST, NT, P, true, 96>(d, c, i_begin, i_end, wpad, lds);
         else if (vec && b.nz == 128) march_tile<ST, NT, P, true, 128>(d, c, i_begin, i_end, wpad, lds);
-        else if (vec) march_tile<ST, NT, P, true, 0>(d, c, i_begin, i_end, wpad, lds);
-        else march_tile<ST, NT, P, false, 0>(d, c, i_begin, i_end, wpad, lds);
+        else if constexpr (KIND != kFixedNz) {
+            if (vec) march_tile<ST, NT, P, true, 0>(d, c, i_begin, i_end, wpad, lds);
+            else if constexpr (KIND == kAny) march_tile<ST, NT, P, false, 0>(d, c, i_begin, i_end, wpad, lds);
+        }
     }
 }
 
@@ -199,10 +226,10 @@ __global__ __launch_bounds__(256) void pw_perturb_kernel(const BatchDomain* __re
 
 __global__ void pw_bump_kernel(unsigned long long* call) { *call += 1ull; }
 
-template <typename ST, int P>
+template <typename ST, int P, int KIND>
 hipError_t launch_batched(const pw_plan* p, const pw_domain_args* args, hipStream_t stream) {
     const BatchState& B = p->batch;
-    auto kern = pw_batched_kernel<ST, 256, P>;
+    auto kern = pw_batched_kernel<ST, 256, P, KIND>;
     static std::once_flag once;
     static hipError_t attr_err = hipSuccess;
     std::call_once(once, [&] {
@@ -216,45 +243,65 @@ hipError_t launch_batched(const pw_plan* p, const pw_domain_args* args, hipStrea
     return hipGetLastError();
 }
 
-template <typename ST, int P>
+template <typename ST, int P, int KIND>
 int occupancy_of(int64_t lds_bytes) {
     int n = 0;
-    auto kern = pw_batched_kernel<ST, 256, P>;
+    auto kern = pw_batched_kernel<ST, 256, P, KIND>;
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
                               160 * 1024);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, 256, (size_t)lds_bytes) != hipSuccess) return 0;
     return n;
 }
 
+template <typename ST, int P>
+int occupancy_kind(int32_t kind, int64_t lds_bytes) {
+    switch (kind) {
+        case kFixedNz: return occupancy_of<ST, P, kFixedNz>(lds_bytes);
+        case kVector: return occupancy_of<ST, P, kVector>(lds_bytes);
+        case kAny: return occupancy_of<ST, P, kAny>(lds_bytes);
+        default: return 0;
+    }
+}
+
 template <typename ST>
-int occupancy_typed(int32_t chunk, int64_t lds_bytes) {
+int occupancy_typed(int32_t chunk, int32_t kind, int64_t lds_bytes) {
     switch (chunk) {
-        case 256: return occupancy_of<ST, 256>(lds_bytes);
-        case 512: return occupancy_of<ST, 512>(lds_bytes);
-        case 1024: return occupancy_of<ST, 1024>(lds_bytes);
+        case 256: return occupancy_kind<ST, 256>(kind, lds_bytes);
+        case 512: return occupancy_kind<ST, 512>(kind, lds_bytes);
+        case 1024: return occupancy_kind<ST, 1024>(kind, lds_bytes);
         default: return 0;
     }
 }
 
 // Resident workgroups per CU of the batched kernel (registers and LDS).
-int batched_occupancy(int32_t storage, int32_t chunk, int64_t lds_bytes) {
+int batched_occupancy(int32_t storage, int32_t chunk, int32_t kind, int64_t lds_bytes) {
     switch (storage) {
-        case PW_F64: return occupancy_typed<double>(chunk, lds_bytes);
-        case PW_F32: return occupancy_typed<float>(chunk, lds_bytes);
-        case PW_BF16: return occupancy_typed<bf16_t>(chunk, lds_bytes);
-        case PW_F16: return occupancy_typed<f16_t>(chunk, lds_bytes);
-        case PW_I16: return occupancy_typed<fx16_t>(chunk, lds_bytes);
-        case PW_I32: return occupancy_typed<fx32_t>(chunk, lds_bytes);
+        case PW_F64: return occupancy_typed<double>(chunk, kind, lds_bytes);
+        case PW_F32: return occupancy_typed<float>(chunk, kind, lds_bytes);
+        case PW_BF16: return occupancy_typed<bf16_t>(chunk, kind, lds_bytes);
+        case PW_F16: return occupancy_typed<f16_t>(chunk, kind, lds_bytes);
+        case PW_I16: return occupancy_typed<fx16_t>(chunk, kind, lds_bytes);
+        case PW_I32: return occupancy_typed<fx32_t>(chunk, kind, lds_bytes);
         default: return 0;
+    }
+}
+
+template <typename ST, int P>
+hipError_t dispatch_kind(const pw_plan* p, const pw_domain_args* args, hipStream_t stream) {
+    switch (p->batch.kind) {
+        case kFixedNz: return launch_batched<ST, P, kFixedNz>(p, args, stream);
+        case kVector: return launch_batched<ST, P, kVector>(p, args, stream);
+        case kAny: return launch_batched<ST, P, kAny>(p, args, stream);
+        default: return hipErrorInvalidValue;
     }
 }
 
 template <typename ST>
 hipError_t dispatch_batched(const pw_plan* p, const pw_domain_args* args, hipStream_t stream) {
     switch (p->batch.launch.chunk) {
-        case 256: return launch_batched<ST, 256>(p, args, stream);
-        case 512: return launch_batched<ST, 512>(p, args, stream);
-        case 1024: return launch_batched<ST, 1024>(p, args, stream);
+        case 256: return dispatch_kind<ST, 256>(p, args, stream);
+        case 512: return dispatch_kind<ST, 512>(p, args, stream);
+        case 1024: return dispatch_kind<ST, 1024>(p, args, stream);
         default: return hipErrorInvalidValue;
     }
 }
@@ -330,7 +377,10 @@ int32_t batched_plan_init(pw_plan* p) {
     if (e != hipSuccess) return report_hip(e);
     const int64_t by_lds = std::max<int64_t>(1, (160 * 1024) / std::max<int64_t>(L.lds_bytes, 1));
     int64_t per_cu = std::min<int64_t>(by_lds, 8);
-    const int occ = batched_occupancy(p->storage, chunk, L.lds_bytes);
+    bool fixed_nz = true;
+    for (const pw_shape& s : p->shapes) fixed_nz = fixed_nz && (s.nz == 64 || s.nz == 96 || s.nz == 128);
+    B.kind = !vec ? kAny : (fixed_nz ? kFixedNz : kVector);
+    const int occ = batched_occupancy(p->storage, chunk, B.kind, L.lds_bytes);
     if (occ > 0) per_cu = std::min<int64_t>(per_cu, occ);
     if (t.wg_per_cu > 0) per_cu = std::min<int64_t>(per_cu, t.wg_per_cu);
     L.workgroups = std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)prop.multiProcessorCount * per_cu));

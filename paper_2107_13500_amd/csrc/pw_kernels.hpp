@@ -299,7 +299,7 @@ struct MarchTile {
     int fsel[NVR];
     const char* gptr[NVR];   // field base + window offset; plane ip adds ip * sx elements
     int loff[NVR];
-    Raw st[NVR];
+    Raw st[2][NVR];          // two planes in flight: plane p lives in set (p - i_begin + 1) % 2
 
     __device__ __forceinline__ int nz() const { return NZ > 0 ? NZ : nz_rt; }
     __device__ __forceinline__ int wpad() const { return NZ > 0 ? WPAD : wpad_rt; }
@@ -356,17 +356,17 @@ struct MarchTile {
         }
     }
 
-    // Issue the global loads of the window of plane ip.
-    __device__ __forceinline__ void load(int64_t ip) {
+    // Issue the global loads of the window of plane ip into `dst`.
+    __device__ __forceinline__ void load_into(Raw* dst, int64_t ip) {
         const int64_t po = ip * d.sx * (int64_t)sizeof(ST);   // uniform byte offset of the plane
 #pragma unroll
         for (int r = 0; r < NVR; ++r) {
-            if (fsel[r] >= 0) st[r] = *reinterpret_cast<const Raw*>(gptr[r] + po);
+            if (fsel[r] >= 0) dst[r] = *reinterpret_cast<const Raw*>(gptr[r] + po);
         }
     }
 
-    // Convert the staged values to the compute type and write them to a slot.
-    __device__ __forceinline__ void put(int sidx) {
+    // Convert staged values to the compute type and write them to a slot.
+    __device__ __forceinline__ void put_from(const Raw* src, int sidx) {
         CT* slot = lds + sidx * slot_elems();
 #pragma unroll
         for (int r = 0; r < NVR; ++r) {
@@ -375,7 +375,7 @@ struct MarchTile {
                     Raw raw;
                     ST e[VW];
                 } cv;
-                cv.raw = st[r];
+                cv.raw = src[r];
                 CT out[VW];
 #pragma unroll
                 for (int n = 0; n < VW; ++n) out[n] = to_compute(cv.e[n]);
@@ -452,51 +452,73 @@ struct MarchTile {
         }
     }
 
-    // One march step: publish plane i+1, prefetch plane i+2, compute plane i.
-    // With three slots the slot of plane i-1 is refilled by the next step, so
-    // a second barrier keeps it until every wave has computed plane i; with
-    // four slots that refill happens one step later, behind the next step's
-    // barrier, and one barrier per plane suffices.
+    // One march step: publish plane i+1, prefetch plane i+3, compute plane i.
+    // Two register sets keep two planes in flight, so each load has two steps
+    // to arrive; SET = (i - i_begin) % 2 holds plane i+1 and then receives
+    // plane i+3.  With three slots the slot of plane i-1 is refilled by the
+    // next step, so a second barrier keeps it until every wave has computed
+    // plane i; with four slots that refill happens one step later, behind the
+    // next step's barrier, and one barrier per plane suffices.
+    template <int SET>
     __device__ __forceinline__ void step(int i, int i_end, int sm, int sc, int sp) {
-        put(sp);
+        put_from(st[SET], sp);
         __syncthreads();
-        if (i + 2 <= i_end + 1) load((int64_t)(i + 2));
+        if (i + 3 <= i_end + 1) load_into(st[SET], (int64_t)(i + 3));
         compute(i, sm, sc, sp);
         if constexpr (NSLOT == 3) __syncthreads();
     }
 
     __device__ __forceinline__ void run(int i_begin, int i_end) {
-        load((int64_t)(i_begin - 1));
-        put(0);
-        load((int64_t)i_begin);
-        put(1);
-        load((int64_t)(i_begin + 1));
+        // the first four planes are requested together, so a tile's start
+        // waits for one memory latency, not several
+        {
+            Raw a[NVR], b[NVR];
+            load_into(a, (int64_t)(i_begin - 1));
+            load_into(b, (int64_t)i_begin);
+            load_into(st[0], (int64_t)(i_begin + 1));   // plane i_begin + 1 <= nx + 1 always exists
+            if (i_begin + 2 <= i_end + 1) load_into(st[1], (int64_t)(i_begin + 2));
+            put_from(a, 0);
+            put_from(b, 1);
+        }
         if constexpr (NZ > 0 && NSLOT == 3) {
-            // ring rotation unrolled: every slot offset is a compile-time constant
-            for (int i = i_begin; i <= i_end; i += 3) {
-                step(i, i_end, 0, 1, 2);
+            // ring rotation and register sets unrolled: slots and sets are
+            // compile-time constants (6 = lcm of 3 slots and 2 sets)
+            for (int i = i_begin; i <= i_end; i += 6) {
+                step<0>(i, i_end, 0, 1, 2);
                 if (i + 1 > i_end) break;
-                step(i + 1, i_end, 1, 2, 0);
+                step<1>(i + 1, i_end, 1, 2, 0);
                 if (i + 2 > i_end) break;
-                step(i + 2, i_end, 2, 0, 1);
+                step<0>(i + 2, i_end, 2, 0, 1);
+                if (i + 3 > i_end) break;
+                step<1>(i + 3, i_end, 0, 1, 2);
+                if (i + 4 > i_end) break;
+                step<0>(i + 4, i_end, 1, 2, 0);
+                if (i + 5 > i_end) break;
+                step<1>(i + 5, i_end, 2, 0, 1);
             }
         } else if constexpr (NZ > 0) {
             for (int i = i_begin; i <= i_end; i += 4) {
-                step(i, i_end, 0, 1, 2);
+                step<0>(i, i_end, 0, 1, 2);
                 if (i + 1 > i_end) break;
-                step(i + 1, i_end, 1, 2, 3);
+                step<1>(i + 1, i_end, 1, 2, 3);
                 if (i + 2 > i_end) break;
-                step(i + 2, i_end, 2, 3, 0);
+                step<0>(i + 2, i_end, 2, 3, 0);
                 if (i + 3 > i_end) break;
-                step(i + 3, i_end, 3, 0, 1);
+                step<1>(i + 3, i_end, 3, 0, 1);
             }
         } else {
             int sm = 0, sc = 1, sp = 2;
-            for (int i = i_begin; i <= i_end; ++i) {
-                step(i, i_end, sm, sc, sp);
+            auto rotate = [&] {
                 sm = sc;
                 sc = sp;
                 sp = sp + 1 == NSLOT ? 0 : sp + 1;
+            };
+            for (int i = i_begin; i <= i_end; i += 2) {
+                step<0>(i, i_end, sm, sc, sp);
+                rotate();
+                if (i + 1 > i_end) break;
+                step<1>(i + 1, i_end, sm, sc, sp);
+                rotate();
             }
         }
         // the next tile of a persistent workgroup refills slots 0 and 1

@@ -41,6 +41,7 @@ struct BatchState {
     unsigned long long* d_errors = nullptr;
     int device = -1;
     bool vec_shapes = false;     // every shape allows 16-byte loads
+    int32_t kind = 2;            // code paths of the batched kernel (BatchKind in pw_batched.hip)
 };
 
 }  // namespace pw

@@ -76,6 +76,75 @@ def test_batched_reduced_storage_matches_single_calls(storage):
             assert torch.equal(a[1:-1, 1:-1], b[1:-1, 1:-1])
 
 
+def offset_copy(t, offset):
+    """A copy of t whose data starts `offset` elements into a fresh buffer."""
+    buf = torch.zeros(t.numel() + offset, dtype=t.dtype, device=t.device)
+    view = buf[offset:].view(t.shape)
+    view.copy_(t)
+    return view
+
+
+@pytest.mark.parametrize("shapes", [[(12, 9, 32), (7, 20, 50), (30, 5, 80), (3, 4, 64)],
+                                    [(12, 9, 33), (7, 20, 51), (5, 5, 64)]],
+                         ids=["other-heights", "odd-heights"])
+@pytest.mark.parametrize("tuning", [{"chunk": 256, "seg": 4}, {"chunk": 512, "seg": 64}], ids=["c256s4", "c512s64"])
+def test_batched_column_heights_outside_the_compiled_set(shapes, tuning):
+    """Heights other than 64 / 96 / 128 take the run-time-height path (vector
+    loads when nz is even for FP64, element loads when it is odd)."""
+    probs = small_problems(shapes, seed=410)
+    batch = BT.DeviceBatch(probs, B.F64, DEV)
+    plan = batch.plan(tuning)
+    batch.advect(plan)
+    torch.cuda.synchronize()
+    assert plan.error_count() == 0
+    for d, p in enumerate(probs):
+        ref = oracle.advect_problem(p)
+        for g, r in zip(batch.host_outputs(d), ref):
+            assert max_rel(g[1:-1, 1:-1], r[1:-1, 1:-1]) <= F64_TOL
+        for a, b in zip(batch.fields[d][3:], single_outputs(batch, d, dict(tuning, variant=B.VARIANT_MARCH))):
+            assert torch.equal(a[1:-1, 1:-1], b[1:-1, 1:-1])
+
+
+def misaligned_records(batch, d):
+    """The batch's records with domain d moved to buffers 8 bytes off a 16-byte boundary."""
+    f = [offset_copy(t, 1) for t in batch.fields[d]]
+    for o in f[3:]:
+        o.fill_(123.0)
+    recs = list(batch.records)
+    p = batch.problems[d]
+    recs[d] = B.domain_record(*f, p.coeffs.tcx, p.coeffs.tcy, *batch.tz[d])
+    assert recs[d].u % 16 == 8
+    return recs, f
+
+
+def test_misaligned_record_in_a_vector_plan_is_skipped_and_counted():
+    probs = small_problems(SMALL[:4], seed=420)
+    batch = BT.DeviceBatch(probs, B.F64, DEV)
+    recs, f = misaligned_records(batch, 1)
+    plan = batch.plan()
+    B.advect_batched(plan, B.domain_args_tensor(recs, DEV))
+    torch.cuda.synchronize()
+    assert plan.error_count() == 1
+    assert all(torch.all(o == 123.0).item() for o in f[3:])
+    for d in (0, 2, 3):
+        ref = oracle.advect_problem(probs[d])
+        for g, r in zip(batch.host_outputs(d), ref):
+            assert max_rel(g[1:-1, 1:-1], r[1:-1, 1:-1]) <= F64_TOL
+
+
+def test_element_aligned_record_in_an_element_plan_is_computed():
+    probs = small_problems([(10, 7, 33), (6, 9, 45)], seed=430)
+    batch = BT.DeviceBatch(probs, B.F64, DEV)
+    recs, f = misaligned_records(batch, 0)
+    plan = batch.plan({"chunk": 256, "seg": 4})
+    B.advect_batched(plan, B.domain_args_tensor(recs, DEV))
+    torch.cuda.synchronize()
+    assert plan.error_count() == 0
+    ref = oracle.advect_problem(probs[0])
+    for g, r in zip(f[3:], ref):
+        assert max_rel(g.cpu().numpy()[1:-1, 1:-1], r[1:-1, 1:-1]) <= F64_TOL
+
+
 def test_shape_mismatch_is_skipped_and_counted():
     probs = small_problems(SMALL[:4], seed=500)
     batch = BT.DeviceBatch(probs, B.F64, DEV)
