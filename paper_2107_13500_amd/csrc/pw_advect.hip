@@ -73,16 +73,20 @@ bool march_possible(const pw_shape& s) {
 }
 
 int32_t auto_seg(const pw_shape& s, int32_t nchunks) {
-    // enough workgroups to fill 256 CUs many times over (about 32 per CU), but
-    // segments long enough that re-reading the two boundary planes stays a few
-    // percent (measured on 2048 x 2048 x 64: 64 planes beat 128 for FP32
-    // compute and tie for FP64)
-    const int64_t target = 8192;
+    // enough workgroups to fill 256 CUs many times over (about 16 per CU),
+    // segments long enough that re-reading the two boundary planes stays a
+    // few percent, and all segments of nearly equal length (measured on
+    // 2048 x 2048 x 64 with two planes in flight: 128 planes beat 64 by 1%
+    // for FP64 and FP32 and tie for the 16-bit types; an uneven split such
+    // as 192 costs 7%)
+    const int64_t target = 4096;
     int64_t seg = (int64_t)s.nx * nchunks / target;
     seg = std::max<int64_t>(seg, 16);
     seg = std::min<int64_t>(seg, 256);
     seg = std::min<int64_t>(seg, s.nx);
-    return (int32_t)std::max<int64_t>(seg, 1);
+    seg = std::max<int64_t>(seg, 1);
+    const int64_t nseg = (s.nx + seg - 1) / seg;
+    return (int32_t)((s.nx + nseg - 1) / nseg);
 }
 
 int32_t resolve_launch(int32_t storage, const pw_shape& s, const pw_tuning& t, Launch* L) {

@@ -97,8 +97,15 @@ __global__ __launch_bounds__(NT) void pw_batched_kernel(const BatchDomain* __res
     const int wgs = q + (x < r ? 1 : 0);                 // workgroups on this XCD
     const int before = x * q + (x < r ? x : r);          // workgroups on lower XCDs
     const int64_t t_end = ntiles * (before + wgs) / G;
+    int dom = -1;
     for (int64_t t = ntiles * before / G + slot; t < t_end; t += wgs) {
-        const int dom = find_domain(table, ndom, t);
+        // tiles only move forward: after the first binary search a short
+        // forward scan finds the domain (usually zero or one step)
+        if (dom < 0) {
+            dom = find_domain(table, ndom, t);
+        } else {
+            while (dom + 1 < ndom && table[dom + 1].tile_begin <= t) ++dom;
+        }
         const BatchDomain b = table[dom];
         const int64_t local = t - b.tile_begin;
         const int c = (int)(local % b.nchunks);
