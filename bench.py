@@ -113,7 +113,7 @@ def measured_traffic(kernel_key, chunk, seg):
 def cpu_baseline(p, threads):
     """The FP64 oracle on the same grid, timed on the host; returns (record, reference outputs)."""
     import oracle
-    reps = 2
+    reps = 6   # about 1 s of wall time (10-20 s of CPU time) on 16 host threads
     t0 = time.perf_counter()
     ref = None
     for _ in range(reps):

@@ -211,7 +211,9 @@ typedef struct pw_domain_args {
      stream     hipStream_t or NULL.
    Every domain is computed exactly as pw_advect computes it (same per-point
    arithmetic), so results are bit-identical to per-domain calls.  Overlap
-   between domains' arrays is not checked. */
+   between domains' arrays is not checked.  The plan holds the persistent
+   kernel's tile cursors: calls on one plan must be ordered (one stream, or
+   synchronised); calls on different plans may run concurrently. */
 int32_t pw_advect_batched(const pw_plan *plan, int32_t ndomains,
                           const pw_domain_args *d_args, void *stream);
 
@@ -241,7 +243,8 @@ int32_t pw_plan_error_count(const pw_plan *plan, unsigned long long *count);
 
 /* Host-resident domains (paper Sec. IV: the accelerator run with the
    host<->device transfers included).  A stream plan owns device buffers,
-   three streams and events for one host domain shape:
+   streams (one kernel stream, one copy stream per field and direction) and
+   events for one host domain shape:
      bulk != 0  one round trip: copy the whole domain in, compute, copy the
                 outputs out, in order on one stream (no overlap);
      bulk == 0  x-slabs of `chunk` planes through a ring of `nbuffers` (2..8)

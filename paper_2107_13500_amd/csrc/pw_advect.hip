@@ -107,6 +107,7 @@ int32_t resolve_launch(int32_t storage, const pw_shape& s, const pw_tuning& t, L
         r.nseg = (s.nx + r.seg - 1) / r.seg;
         r.wpad = ((chunk + 2 * s.nz) + 3) / 4 * 4;
         r.lds_bytes = march_lds_bytes(storage, r.wpad);
+        if (r.lds_bytes > kMaxDynamicLds) return PW_ERR_UNSUPPORTED;
         r.workgroups = (int64_t)r.nchunks * r.nseg;
         if (r.workgroups >= (int64_t(1) << 31)) return PW_ERR_INVALID_ARG;
     } else {
@@ -136,7 +137,7 @@ hipError_t launch_march(const DomainArgs& d, const Launch& L, hipStream_t stream
     static hipError_t attr_err = hipSuccess;
     std::call_once(once, [&] {
         attr_err = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynamicLds);
     });
     if (attr_err != hipSuccess) return attr_err;
     MarchGeom g{L.nchunks, L.nseg, L.seg, L.wpad};

@@ -24,6 +24,8 @@
 namespace pw {
 
 constexpr int kMarchMaxNz = 256;   // largest column the march variant accepts
+constexpr int kLdsPerCu = 160 * 1024;           // gfx950 LDS per CU (and per workgroup)
+constexpr int kMaxDynamicLds = kLdsPerCu - 1024;   // leaves room for a kernel's small static LDS
 constexpr int kNumXcd = 8;         // MI355X: 8 accelerator complex dies, one L2 each
 
 // Everything a kernel needs about one domain (passed by value).
