@@ -211,9 +211,7 @@ typedef struct pw_domain_args {
      stream     hipStream_t or NULL.
    Every domain is computed exactly as pw_advect computes it (same per-point
    arithmetic), so results are bit-identical to per-domain calls.  Overlap
-   between domains' arrays is not checked.  The plan holds the persistent
-   kernel's tile cursors: calls on one plan must be ordered (one stream, or
-   synchronised); calls on different plans may run concurrently. */
+   between domains' arrays is not checked. */
 int32_t pw_advect_batched(const pw_plan *plan, int32_t ndomains,
                           const pw_domain_args *d_args, void *stream);
 

@@ -78,93 +78,62 @@ __device__ __forceinline__ bool aligned16(const void* p) { return (reinterpret_c
 // is not is skipped and counted like a shape mismatch.
 enum BatchKind { kFixedNz = 0, kVector = 1, kAny = 2 };
 
-// Scheduling words of a batched plan (device memory, zero between launches):
-// one tile cursor per XCD, each on its own 64-byte line, then the count of
-// finished workgroups.
-constexpr int kSchedStride = 16;                      // uint32 words per cursor line
-constexpr int kSchedWords = (kNumXcd + 1) * kSchedStride;
-
 template <typename ST, int NT, int P, int KIND>
 __global__ __launch_bounds__(NT) void pw_batched_kernel(const BatchDomain* __restrict__ table, int ndom,
                                                         int64_t ntiles, const pw_domain_args* __restrict__ args,
                                                         int seg, unsigned long long* errors,
-                                                        unsigned int* sched, int vec_shapes) {
+                                                        int vec_shapes) {
     using CT = typename compute_of<ST>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     CT* lds = reinterpret_cast<CT*>(smem_raw);
-    __shared__ unsigned int s_cur;
-    // Workgroups are dispatched round-robin over the XCDs.  Each XCD owns a
-    // contiguous share of the tile range, so the tiles in flight on one XCD
-    // are neighbouring chunks and segments of the same domains and share
-    // their halo columns and planes in its L2.  Within the share, workgroups
-    // take the next tile from the XCD's cursor as they finish (tiles differ
-    // in size: ragged chunks and segments), requesting it one tile ahead so
-    // the atomic's latency hides behind the current tile.
+    // Workgroups are dispatched round-robin over the XCDs.  Give each XCD a
+    // contiguous share of the tile range, walked by its own workgroups, so
+    // the tiles in flight on one XCD are neighbouring chunks and segments of
+    // the same domains and share their halo columns and planes in its L2.
     const int G = (int)gridDim.x;
     const int x = (int)blockIdx.x % kNumXcd;
+    const int slot = (int)blockIdx.x / kNumXcd;
     const int q = G / kNumXcd, r = G % kNumXcd;
     const int wgs = q + (x < r ? 1 : 0);                 // workgroups on this XCD
     const int before = x * q + (x < r ? x : r);          // workgroups on lower XCDs
-    const int64_t t_begin = ntiles * before / G;
     const int64_t t_end = ntiles * (before + wgs) / G;
-    unsigned int* cursor = sched + x * kSchedStride;
-    unsigned int ahead = 0;
-    if (threadIdx.x == 0) s_cur = atomicAdd(cursor, 1u);
-    __syncthreads();
     int dom = -1;
-    for (;;) {
-        const int64_t t = t_begin + (int64_t)s_cur;
-        if (threadIdx.x == 0) ahead = atomicAdd(cursor, 1u);   // the tile after this one
-        __syncthreads();   // every thread has read s_cur
-        if (t >= t_end) break;
-        {
-            // tiles only move forward: after the first binary search a short
-            // forward scan finds the domain (usually zero or one step)
-            if (dom < 0) {
-                dom = find_domain(table, ndom, t);
-            } else {
-                while (dom + 1 < ndom && table[dom + 1].tile_begin <= t) ++dom;
-            }
-            const BatchDomain b = table[dom];
-            const int64_t local = t - b.tile_begin;
-            const int c = (int)(local % b.nchunks);
-            const int s = (int)(local / b.nchunks);
-            const pw_domain_args& a = args[dom];
-            if (!shape_matches(a.shape, b) || !a.u || !a.v || !a.w || !a.su || !a.sv || !a.sw) {
-                if (threadIdx.x == 0 && local == 0) atomicAdd(errors, 1ull);
-                goto next_tile;   // uniform over the workgroup
-            }
-            const DomainArgs d = domain_from<ST>(a, b);
-            const int i_begin = 1 + s * seg;
-            const int i_end = min(i_begin + seg - 1, b.nx);
-            const bool vec = vec_shapes && aligned16(a.u) && aligned16(a.v) && aligned16(a.w) && aligned16(a.su) &&
-                             aligned16(a.sv) && aligned16(a.sw);
-            if (KIND != kAny && !vec) {
-                if (threadIdx.x == 0 && local == 0) atomicAdd(errors, 1ull);
-                goto next_tile;   // uniform over the workgroup
-            }
-            const int wpad = round_up4(P + 2 * b.nz);
-            if (vec && b.nz == 64) march_tile<ST, NT, P, true, 64>(d, c, i_begin, i_end, wpad, lds);
-            else if (vec && b.nz == 96) march_tile<ST, NT, P, true, 96>(d, c, i_begin, i_end, wpad, lds);
-            else if (vec && b.nz == 128) march_tile<ST, NT, P, true, 128>(d, c, i_begin, i_end, wpad, lds);
-            else if constexpr (KIND != kFixedNz) {
-                if (vec) march_tile<ST, NT, P, true, 0>(d, c, i_begin, i_end, wpad, lds);
-                else if constexpr (KIND == kAny) march_tile<ST, NT, P, false, 0>(d, c, i_begin, i_end, wpad, lds);
-            }
+    for (int64_t t = ntiles * before / G + slot; t < t_end; t += wgs) {
+        // tiles only move forward: after the first binary search a short
+        // forward scan finds the domain (usually zero or one step)
+        if (dom < 0) {
+            dom = find_domain(table, ndom, t);
+        } else {
+            while (dom + 1 < ndom && table[dom + 1].tile_begin <= t) ++dom;
         }
-    next_tile:
-        if (threadIdx.x == 0) s_cur = ahead;
-        __syncthreads();   // the next tile index is visible to every thread
-    }
-    // The last workgroup to finish rewinds the cursors for the next launch
-    // (launches on one plan are stream-ordered; every cursor increment of
-    // this launch precedes its workgroup's increment of the finish count).
-    if (threadIdx.x == 0) {
-        __threadfence();
-        if (atomicAdd(sched + kNumXcd * kSchedStride, 1u) == (unsigned int)G - 1) {
-            for (int i = 0; i < kNumXcd; ++i) atomicExch(sched + i * kSchedStride, 0u);
-            atomicExch(sched + kNumXcd * kSchedStride, 0u);
-            __threadfence();
+        const BatchDomain b = table[dom];
+        const int64_t local = t - b.tile_begin;
+        const int c = (int)(local % b.nchunks);
+        const int s = (int)(local / b.nchunks);
+        const pw_domain_args& a = args[dom];
+        if (!shape_matches(a.shape, b) || !a.u || !a.v || !a.w || !a.su || !a.sv || !a.sw) {
+            if (threadIdx.x == 0 && local == 0) atomicAdd(errors, 1ull);
+            continue;   // uniform over the workgroup
+        }
+        const DomainArgs d = domain_from<ST>(a, b);
+        const int i_begin = 1 + s * seg;
+        const int i_end = min(i_begin + seg - 1, b.nx);
+        const bool vec = vec_shapes && aligned16(a.u) && aligned16(a.v) && aligned16(a.w) && aligned16(a.su) &&
+                         aligned16(a.sv) && aligned16(a.sw);
+        if (KIND != kAny && !vec) {
+            if (threadIdx.x == 0 && local == 0) atomicAdd(errors, 1ull);
+            continue;   // uniform over the workgroup
+        }
+        const int wpad = round_up4(P + 2 * b.nz);
+        // short tiles leave less time to hide a plane's latency: FP64
+        // compute (three LDS slots) keeps three planes in flight
+        constexpr int D = march_slots<CT>() == 3 ? 3 : 2;
+        if (vec && b.nz == 64) march_tile<ST, NT, P, true, 64, D>(d, c, i_begin, i_end, wpad, lds);
+        else if (vec && b.nz == 96) march_tile<ST, NT, P, true, 96, D>(d, c, i_begin, i_end, wpad, lds);
+        else if (vec && b.nz == 128) march_tile<ST, NT, P, true, 128, D>(d, c, i_begin, i_end, wpad, lds);
+        else if constexpr (KIND != kFixedNz) {
+            if (vec) march_tile<ST, NT, P, true, 0, D>(d, c, i_begin, i_end, wpad, lds);
+            else if constexpr (KIND == kAny) march_tile<ST, NT, P, false, 0, D>(d, c, i_begin, i_end, wpad, lds);
         }
     }
 }
@@ -279,7 +248,7 @@ hipError_t launch_batched(const pw_plan* p, const pw_domain_args* args, hipStrea
     });
     if (attr_err != hipSuccess) return attr_err;
     hipLaunchKernelGGL(kern, dim3((unsigned)B.launch.workgroups), dim3(256), (size_t)B.launch.lds_bytes, stream,
-                       B.d_table, p->ndomains, B.launch.tiles, args, B.launch.seg, B.d_errors, B.d_sched,
+                       B.d_table, p->ndomains, B.launch.tiles, args, B.launch.seg, B.d_errors,
                        B.vec_shapes ? 1 : 0);
     return hipGetLastError();
 }
@@ -431,25 +400,20 @@ int32_t batched_plan_init(pw_plan* p) {
 
     void* mem = nullptr;
     const size_t tbytes = sizeof(BatchDomain) * table.size();
-    // one allocation: the tile table, then the error count (8 bytes, padded
-    // to 64), then the scheduling words
+    // one allocation: the tile table, then the error count
     const size_t off_err = (tbytes + 63) / 64 * 64;
-    const size_t off_sched = off_err + 64;
-    const size_t sched_bytes = sizeof(unsigned int) * kSchedWords;
-    e = hipMalloc(&mem, off_sched + sched_bytes);
+    e = hipMalloc(&mem, off_err + 64);
     if (e == hipErrorOutOfMemory) return PW_ERR_OUT_OF_MEMORY;
     if (e != hipSuccess) return report_hip(e);
     B.d_table = static_cast<BatchDomain*>(mem);
     B.d_errors = reinterpret_cast<unsigned long long*>(static_cast<char*>(mem) + off_err);
-    B.d_sched = reinterpret_cast<unsigned int*>(static_cast<char*>(mem) + off_sched);
     e = hipMemcpy(B.d_table, table.data(), tbytes, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(static_cast<char*>(mem) + off_err, 0, off_sched + sched_bytes - off_err);
+    if (e == hipSuccess) e = hipMemset(B.d_errors, 0, sizeof(unsigned long long));
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);   // zeroed before any launch on another stream
     if (e != hipSuccess) {
         (void)hipFree(mem);
         B.d_table = nullptr;
         B.d_errors = nullptr;
-        B.d_sched = nullptr;
         return report_hip(e);
     }
     B.launch = L;
@@ -463,7 +427,6 @@ int32_t batched_plan_free(pw_plan* p) {
         hipError_t e = hipFree(p->batch.d_table);
         p->batch.d_table = nullptr;
         p->batch.d_errors = nullptr;
-        p->batch.d_sched = nullptr;
         if (e != hipSuccess) return report_hip(e);
     }
     return PW_OK;

@@ -226,6 +226,7 @@ struct LdsAcc {
 };
 
 constexpr int round_up4(int x) { return (x + 3) / 4 * 4; }
+constexpr int gcd_int(int a, int b) { return b == 0 ? a : gcd_int(b, a % b); }
 
 template <typename CT> struct vec2_of;
 template <> struct vec2_of<double> { using type = f64x2; };
@@ -267,7 +268,7 @@ template <typename CT> constexpr int march_slots() { return sizeof(CT) == 4 ? 4 
 // holds barriers); `lds` must hold 3 * march_slots<CT>() * wpad compute-type
 // elements.
 // NZ > 0: the domain's nz equals NZ and wpad equals round_up4(P + 2 NZ).
-template <typename ST, int NT, int P, bool VEC, int NZ>
+template <typename ST, int NT, int P, bool VEC, int NZ, int DIST = 2>
 struct MarchTile {
     using CT = typename compute_of<ST>::type;
     static constexpr int VW = VEC ? int(16 / sizeof(ST)) : 1;            // elements per load
@@ -301,7 +302,11 @@ struct MarchTile {
     int fsel[NVR];
     const char* gptr[NVR];   // field base + window offset; plane ip adds ip * sx elements
     int loff[NVR];
-    Raw st[2][NVR];          // two planes in flight: plane p lives in set (p - i_begin + 1) % 2
+    // DIST planes in flight: plane p lives in register set (p - i_begin + 1) % DIST
+    static_assert(DIST == 2 || DIST == 3, "two or three planes in flight");
+    static constexpr int UNROLL = NSLOT * DIST / gcd_int(NSLOT, DIST);   // steps until slots and sets repeat
+    static_assert(UNROLL <= 6, "unrolled block too long");
+    Raw st[DIST][NVR];
 
     __device__ __forceinline__ int nz() const { return NZ > 0 ? NZ : nz_rt; }
     __device__ __forceinline__ int wpad() const { return NZ > 0 ? WPAD : wpad_rt; }
@@ -454,73 +459,75 @@ struct MarchTile {
         }
     }
 
-    // One march step: publish plane i+1, prefetch plane i+3, compute plane i.
-    // Two register sets keep two planes in flight, so each load has two steps
-    // to arrive; SET = (i - i_begin) % 2 holds plane i+1 and then receives
-    // plane i+3.  With three slots the slot of plane i-1 is refilled by the
-    // next step, so a second barrier keeps it until every wave has computed
-    // plane i; with four slots that refill happens one step later, behind the
-    // next step's barrier, and one barrier per plane suffices.
+    // One march step: publish plane i+1, prefetch plane i+1+DIST, compute
+    // plane i.  DIST register sets keep DIST planes in flight, so each load
+    // has DIST steps to arrive; SET = (i - i_begin) % DIST holds plane i+1
+    // and then receives plane i+1+DIST.  With three slots the slot of plane
+    // i-1 is refilled by the next step, so a second barrier keeps it until
+    // every wave has computed plane i; with four slots that refill happens
+    // one step later, behind the next step's barrier, and one barrier per
+    // plane suffices.
     template <int SET>
     __device__ __forceinline__ void step(int i, int i_end, int sm, int sc, int sp) {
         put_from(st[SET], sp);
         __syncthreads();
-        if (i + 3 <= i_end + 1) load_into(st[SET], (int64_t)(i + 3));
+        if (i + 1 + DIST <= i_end + 1) load_into(st[SET], (int64_t)(i + 1 + DIST));
         compute(i, sm, sc, sp);
         if constexpr (NSLOT == 3) __syncthreads();
     }
 
+    // Steps R .. UNROLL-1 of one unrolled block starting at plane i; slots and
+    // register sets are compile-time constants.  Returns false past i_end.
+    template <int R>
+    __device__ __forceinline__ bool block(int i, int i_end) {
+        if constexpr (R == UNROLL) {
+            return true;
+        } else {
+            if (i + R > i_end) return false;
+            step<R % DIST>(i + R, i_end, R % NSLOT, (R + 1) % NSLOT, (R + 2) % NSLOT);
+            return block<R + 1>(i, i_end);
+        }
+    }
+
+    // Run-time slots (any column height): DIST steps per iteration so the
+    // register sets stay compile-time.
+    template <int R>
+    __device__ __forceinline__ bool block_rt(int i, int i_end, int& sm, int& sc, int& sp) {
+        if constexpr (R == DIST) {
+            return true;
+        } else {
+            if (i + R > i_end) return false;
+            step<R>(i + R, i_end, sm, sc, sp);
+            sm = sc;
+            sc = sp;
+            sp = sp + 1 == NSLOT ? 0 : sp + 1;
+            return block_rt<R + 1>(i, i_end, sm, sc, sp);
+        }
+    }
+
     __device__ __forceinline__ void run(int i_begin, int i_end) {
-        // the first four planes are requested together, so a tile's start
-        // waits for one memory latency, not several
+        // the first planes are requested together, so a tile's start waits
+        // for one memory latency, not several
         {
             Raw a[NVR], b[NVR];
             load_into(a, (int64_t)(i_begin - 1));
             load_into(b, (int64_t)i_begin);
             load_into(st[0], (int64_t)(i_begin + 1));   // plane i_begin + 1 <= nx + 1 always exists
-            if (i_begin + 2 <= i_end + 1) load_into(st[1], (int64_t)(i_begin + 2));
+#pragma unroll
+            for (int q = 1; q < DIST; ++q) {
+                if (i_begin + 1 + q <= i_end + 1) load_into(st[q], (int64_t)(i_begin + 1 + q));
+            }
             put_from(a, 0);
             put_from(b, 1);
         }
-        if constexpr (NZ > 0 && NSLOT == 3) {
-            // ring rotation and register sets unrolled: slots and sets are
-            // compile-time constants (6 = lcm of 3 slots and 2 sets)
-            for (int i = i_begin; i <= i_end; i += 6) {
-                step<0>(i, i_end, 0, 1, 2);
-                if (i + 1 > i_end) break;
-                step<1>(i + 1, i_end, 1, 2, 0);
-                if (i + 2 > i_end) break;
-                step<0>(i + 2, i_end, 2, 0, 1);
-                if (i + 3 > i_end) break;
-                step<1>(i + 3, i_end, 0, 1, 2);
-                if (i + 4 > i_end) break;
-                step<0>(i + 4, i_end, 1, 2, 0);
-                if (i + 5 > i_end) break;
-                step<1>(i + 5, i_end, 2, 0, 1);
-            }
-        } else if constexpr (NZ > 0) {
-            for (int i = i_begin; i <= i_end; i += 4) {
-                step<0>(i, i_end, 0, 1, 2);
-                if (i + 1 > i_end) break;
-                step<1>(i + 1, i_end, 1, 2, 3);
-                if (i + 2 > i_end) break;
-                step<0>(i + 2, i_end, 2, 3, 0);
-                if (i + 3 > i_end) break;
-                step<1>(i + 3, i_end, 3, 0, 1);
+        if constexpr (NZ > 0) {
+            for (int i = i_begin;; i += UNROLL) {
+                if (!block<0>(i, i_end)) break;
             }
         } else {
             int sm = 0, sc = 1, sp = 2;
-            auto rotate = [&] {
-                sm = sc;
-                sc = sp;
-                sp = sp + 1 == NSLOT ? 0 : sp + 1;
-            };
-            for (int i = i_begin; i <= i_end; i += 2) {
-                step<0>(i, i_end, sm, sc, sp);
-                rotate();
-                if (i + 1 > i_end) break;
-                step<1>(i + 1, i_end, sm, sc, sp);
-                rotate();
+            for (int i = i_begin;; i += DIST) {
+                if (!block_rt<0>(i, i_end, sm, sc, sp)) break;
             }
         }
         // the next tile of a persistent workgroup refills slots 0 and 1
@@ -528,10 +535,10 @@ struct MarchTile {
     }
 };
 
-template <typename ST, int NT, int P, bool VEC, int NZ>
+template <typename ST, int NT, int P, bool VEC, int NZ, int DIST = 2>
 __device__ __forceinline__ void march_tile(const DomainArgs& d, int c, int i_begin, int i_end, int wpad,
                                            typename compute_of<ST>::type* lds) {
-    MarchTile<ST, NT, P, VEC, NZ> t(d, c, wpad, lds);
+    MarchTile<ST, NT, P, VEC, NZ, DIST> t(d, c, wpad, lds);
     t.run(i_begin, i_end);
 }
 

@@ -39,7 +39,6 @@ struct BatchState {
     Launch launch;               // shared kernel shape (chunk, seg, wpad for the largest nz)
     BatchDomain* d_table = nullptr;
     unsigned long long* d_errors = nullptr;
-    unsigned int* d_sched = nullptr;   // tile cursors of the persistent kernel (same allocation)
     int device = -1;
     bool vec_shapes = false;     // every shape allows 16-byte loads
     int32_t kind = 2;            // code paths of the batched kernel (BatchKind in pw_batched.hip)
