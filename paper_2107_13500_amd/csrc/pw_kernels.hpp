@@ -5,16 +5,17 @@
 // march   the HBM-streaming kernel.  With packed columns (sy = nz) each x plane
 //         is one contiguous run of (ny + 2) * nz elements, so a workgroup owns a
 //         contiguous chunk of P points of that (j, k) run and walks along x.  It
-//         keeps the three planes i-1, i, i+1 of u, v, w in a ring of LDS slots
-//         (the GPU form of the paper's three-slice shift buffer, Sec. III): each
-//         step loads one new plane window [p0 - nz, p0 + P + nz) -- the chunk
-//         plus one column of y halo on each side -- into registers while the
-//         current plane is computed, so every input element crosses HBM about
-//         once and the loads of plane i+2 overlap the arithmetic of plane i.
-//         With a compile-time column height every LDS offset is an immediate,
-//         the ring rotation is unrolled so the slots are compile-time too, and
-//         each thread computes two consecutive levels, sharing their neighbour
-//         reads and storing both results with one vector store.
+//         keeps the planes i-1, i, i+1 of u, v, w in a ring of LDS slots (the
+//         GPU form of the paper's three-slice shift buffer, Sec. III; a fourth
+//         slot for FP32 compute saves one barrier per plane).  The window of a
+//         plane is [p0 - nz, p0 + P + nz) -- the chunk plus one column of y
+//         halo on each side -- so every input element crosses HBM about once.
+//         Two or three later planes are in flight in registers while a plane
+//         is computed.  With a compile-time column height every LDS offset is
+//         an immediate, the ring rotation is unrolled so slots and register
+//         sets are compile-time too, and each thread computes two consecutive
+//         levels, sharing their neighbour reads and storing both results with
+//         one vector store.
 #pragma once
 
 #include <type_traits>
