@@ -125,12 +125,16 @@ __global__ __launch_bounds__(NT) void pw_batched_kernel(const BatchDomain* __res
             continue;   // uniform over the workgroup
         }
         const int wpad = round_up4(P + 2 * b.nz);
-        // short tiles leave less time to hide a plane's latency: FP64
-        // compute (three LDS slots) keeps three planes in flight
+        // Short tiles leave less time to hide a plane's latency: FP64
+        // compute (three LDS slots) keeps three planes in flight, and every
+        // storage type takes the branch-free data movement, whose exact
+        // outstanding-load counts keep those planes in flight (measured on
+        // the 384-domain batch: FP64 1.45 -> 1.22 ms, FP32 0.75 -> 0.64 ms).
         constexpr int D = march_slots<CT>() == 3 ? 3 : 2;
-        if (vec && b.nz == 64) march_tile<ST, NT, P, true, 64, D>(d, c, i_begin, i_end, wpad, lds);
-        else if (vec && b.nz == 96) march_tile<ST, NT, P, true, 96, D>(d, c, i_begin, i_end, wpad, lds);
-        else if (vec && b.nz == 128) march_tile<ST, NT, P, true, 128, D>(d, c, i_begin, i_end, wpad, lds);
+        constexpr bool X = true;
+        if (vec && b.nz == 64) march_tile<ST, NT, P, true, 64, D, X>(d, c, i_begin, i_end, wpad, lds);
+        else if (vec && b.nz == 96) march_tile<ST, NT, P, true, 96, D, X>(d, c, i_begin, i_end, wpad, lds);
+        else if (vec && b.nz == 128) march_tile<ST, NT, P, true, 128, D, X>(d, c, i_begin, i_end, wpad, lds);
         else if constexpr (KIND != kFixedNz) {
             if (vec) march_tile<ST, NT, P, true, 0, D>(d, c, i_begin, i_end, wpad, lds);
             else if constexpr (KIND == kAny) march_tile<ST, NT, P, false, 0, D>(d, c, i_begin, i_end, wpad, lds);

@@ -269,7 +269,7 @@ template <typename CT> constexpr int march_slots() { return sizeof(CT) == 4 ? 4 
 // holds barriers); `lds` must hold 3 * march_slots<CT>() * wpad compute-type
 // elements.
 // NZ > 0: the domain's nz equals NZ and wpad equals round_up4(P + 2 NZ).
-template <typename ST, int NT, int P, bool VEC, int NZ, int DIST = 2>
+template <typename ST, int NT, int P, bool VEC, int NZ, int DIST = 2, bool FORCE_EXACT = false>
 struct MarchTile {
     using CT = typename compute_of<ST>::type;
     // Elements per load: as many as fill 16 bytes of LDS in the compute type,
@@ -287,7 +287,7 @@ struct MarchTile {
     // and FP64 storage are bound by HBM and keep the branches, which cost
     // fewer registers (measured: 4% faster for them, 4-23% slower for the
     // converting types).
-    static constexpr bool EXACT = NZ > 0 && sizeof(ST) < sizeof(CT);
+    static constexpr bool EXACT = NZ > 0 && (FORCE_EXACT || sizeof(ST) < sizeof(CT));
     static constexpr int NSLOT = march_slots<CT>();                       // planes in the LDS ring
     static_assert(!VEC || VW * sizeof(ST) == 16 || VW * sizeof(ST) == 8, "8- or 16-byte loads");
     using Raw = typename std::conditional<VEC, typename std::conditional<VW * sizeof(ST) == 16, uint4, uint2>::type,
@@ -560,10 +560,10 @@ struct MarchTile {
     }
 };
 
-template <typename ST, int NT, int P, bool VEC, int NZ, int DIST = 2>
+template <typename ST, int NT, int P, bool VEC, int NZ, int DIST = 2, bool FORCE_EXACT = false>
 __device__ __forceinline__ void march_tile(const DomainArgs& d, int c, int i_begin, int i_end, int wpad,
                                            typename compute_of<ST>::type* lds) {
-    MarchTile<ST, NT, P, VEC, NZ, DIST> t(d, c, wpad, lds);
+    MarchTile<ST, NT, P, VEC, NZ, DIST, FORCE_EXACT> t(d, c, wpad, lds);
     t.run(i_begin, i_end);
 }
 
