@@ -295,7 +295,14 @@ def power_leg(step, ms_per_step, npoints, stream, log, seconds=6.0):
     the idle power before it; energy efficiency in Gpoints per joule."""
     import threading
     import torch
-    idle = [x for x in (read_power_w() for _ in range(3)) if x is not None]
+    torch.cuda.synchronize()
+    time.sleep(2.0)   # the reading averages over a window: let earlier legs' load fall off
+    idle = []
+    for _ in range(5):
+        w = read_power_w()
+        if w is not None:
+            idle.append(w)
+        time.sleep(0.2)
     if not idle:
         return {"available": False, "reason": "amd-smi socket power not readable"}
     samples, stop = [], threading.Event()
