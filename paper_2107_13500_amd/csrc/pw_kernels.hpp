@@ -264,6 +264,43 @@ struct PairAcc {
 // three for FP64, whose larger slots would otherwise cost occupancy.
 template <typename CT> constexpr int march_slots() { return sizeof(CT) == 4 ? 4 : 3; }
 
+// The aligned two-level blocks a pair of levels reads: field F, row offset dj,
+// plane offset di, block b in {-2, 0, 2} levels from the pair's start.  The
+// stencil's reads (pw_point) per (field, dj, di) as a mask of level offsets
+// dk (bit 0: dk = -1, bit 1: dk = 0, bit 2: dk = +1); a read at dk touches
+// block -2 (dk = -1, first point), block 0 (every dk) and block 2 (dk = +1,
+// second point).
+constexpr int pair_dk_mask(int F, int dj, int di) {
+    // [field][dj + 1][di + 1]
+    constexpr int mask[3][3][3] = {{{0, 2, 0}, {6, 7, 2}, {2, 2, 0}},    // u
+                                   {{0, 6, 2}, {2, 7, 2}, {0, 2, 0}},    // v
+                                   {{0, 2, 0}, {2, 7, 3}, {0, 3, 0}}};   // w
+    return mask[F][dj + 1][di + 1];
+}
+constexpr bool pair_block_used(int F, int dj, int di, int b) {
+    return b == -2 ? (pair_dk_mask(F, dj, di) & 1) != 0
+                   : (b == 0 ? pair_dk_mask(F, dj, di) != 0 : (pair_dk_mask(F, dj, di) & 4) != 0);
+}
+constexpr int pair_key(int F, int dj, int di, int b) { return ((F * 3 + dj + 1) * 3 + di + 1) * 3 + b / 2 + 1; }
+constexpr int pair_carry_key(int F, int dj, int b) { return (F * 3 + dj + 1) * 3 + b / 2 + 1; }
+
+// Pair reads from blocks already held in registers (indexed by pair_key).
+template <typename CT, int O>
+struct CachedPairAcc {
+    using V2 = typename vec2_of<CT>::type;
+    const V2* blk;
+    template <int F, int dk, int dj, int di>
+    __device__ __forceinline__ CT get() const {
+        constexpr int e = O + dk;
+        constexpr int start = e < 0 ? -2 : (e >= 2 ? 2 : 0);
+        static_assert(pair_block_used(F, dj, di, start), "block missing from the pair block table");
+        return blk[pair_key(F, dj, di, start)][e - start];
+    }
+    template <int dk, int dj, int di> __device__ __forceinline__ CT u() const { return get<0, dk, dj, di>(); }
+    template <int dk, int dj, int di> __device__ __forceinline__ CT v() const { return get<1, dk, dj, di>(); }
+    template <int dk, int dj, int di> __device__ __forceinline__ CT w() const { return get<2, dk, dj, di>(); }
+};
+
 // One (chunk, segment) tile of the march: chunk c of the interior (j, k) run,
 // planes i_begin .. i_end.  Every thread of the workgroup must run it (it
 // holds barriers); `lds` must hold 3 * march_slots<CT>() * wpad compute-type
@@ -312,6 +349,15 @@ struct MarchTile {
     // plane).  FP64 pairs are single 16-byte reads with immediate offsets.
     static constexpr bool BASES = PAIR && sizeof(CT) == 4;
     int pbo[BASES ? PPT / 2 : 1][3 * NSLOT];
+    // CARRY (converting storage with FP32 compute): blocks read at plane i as
+    // "this plane" or "next plane" are kept in registers and reused at plane
+    // i+1 as "previous plane" or "this plane", so a pair reads 17 of its 27
+    // blocks from LDS instead of all of them.  cm: blocks for di = -1, c0:
+    // blocks for di = 0, both indexed by pair_carry_key.
+    static constexpr bool CARRY = BASES && EXACT;
+    using V2 = typename vec2_of<CT>::type;
+    V2 cm[CARRY ? PPT / 2 : 1][27];
+    V2 c0[CARRY ? PPT / 2 : 1][27];
     int fsel[NVR];
     const char* gptr[NVR];   // field base + window offset; plane ip adds ip * sx elements
     int loff[NVR];
@@ -425,18 +471,75 @@ struct MarchTile {
         }
     }
 
+    // CARRY: this step's blocks of pair pq, from the carried registers where
+    // the previous step read them, else from LDS (slots sm, sc, sp hold planes
+    // i-1, i, i+1).  Compile-time loop over all 81 keys; unused keys vanish.
+    template <int K>
+    __device__ __forceinline__ void gather_blocks(V2* blk, int pq, int sm, int sc, int sp) {
+        if constexpr (K < 81) {
+            constexpr int F = K / 27, dj = (K / 9) % 3 - 1, di = (K / 3) % 3 - 1, b = (K % 3 - 1) * 2;
+            if constexpr (pair_block_used(F, dj, di, b)) {
+                if constexpr (di == -1 && pair_block_used(F, dj, 0, b)) {
+                    blk[K] = cm[pq][pair_carry_key(F, dj, b)];
+                } else if constexpr (di == 0 && pair_block_used(F, dj, 1, b)) {
+                    blk[K] = c0[pq][pair_carry_key(F, dj, b)];
+                } else {
+                    const int slot = di < 0 ? sm : (di > 0 ? sp : sc);
+                    blk[K] = *reinterpret_cast<const V2*>(lds + pbo[pq][slot * 3 + F] + dj * NZ + b);
+                }
+            }
+            gather_blocks<K + 1>(blk, pq, sm, sc, sp);
+        }
+    }
+    // CARRY: keep this step's blocks that the next step reuses.
+    template <int K>
+    __device__ __forceinline__ void keep_blocks(const V2* blk, int pq) {
+        if constexpr (K < 27) {
+            constexpr int F = K / 9, dj = (K / 3) % 3 - 1, b = (K % 3 - 1) * 2;
+            if constexpr (pair_block_used(F, dj, -1, b) && pair_block_used(F, dj, 0, b))
+                cm[pq][K] = blk[pair_key(F, dj, 0, b)];
+            if constexpr (pair_block_used(F, dj, 0, b) && pair_block_used(F, dj, 1, b))
+                c0[pq][K] = blk[pair_key(F, dj, 1, b)];
+            keep_blocks<K + 1>(blk, pq);
+        }
+    }
+    // CARRY: before a tile's first step, load the carried blocks from planes
+    // i_begin - 1 (slot 0) and i_begin (slot 1).
+    template <int K>
+    __device__ __forceinline__ void prime_blocks(int pq) {
+        if constexpr (K < 27) {
+            constexpr int F = K / 9, dj = (K / 3) % 3 - 1, b = (K % 3 - 1) * 2;
+            if constexpr (pair_block_used(F, dj, -1, b) && pair_block_used(F, dj, 0, b))
+                cm[pq][K] = *reinterpret_cast<const V2*>(lds + pbo[pq][0 * 3 + F] + dj * NZ + b);
+            if constexpr (pair_block_used(F, dj, 0, b) && pair_block_used(F, dj, 1, b))
+                c0[pq][K] = *reinterpret_cast<const V2*>(lds + pbo[pq][1 * 3 + F] + dj * NZ + b);
+            prime_blocks<K + 1>(pq);
+        }
+    }
+
     // Compute plane i from the slots sm (plane i-1), sc (plane i), sp (plane i+1).
     __device__ __forceinline__ void compute(int i, int sm, int sc, int sp) {
         const int64_t obase = (int64_t)i * d.sx + wb;
         const int se = slot_elems();
         using AR = typename arith_of<ST>::type;
         CT res[PPT][3];
+        V2 blk[CARRY ? PPT / 2 : 1][81];   // CARRY: this step's blocks, indexed by pair_key
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
             const int l = li[q];
             const PointCoefs<CT> c{hx[0], hy[0], zc[q][0], zc[q][1], hy[1], hx[1], zc[q][2], zc[q][3],
                                    hx[2], hy[2], zc[q][4], zc[q][5]};
-            if constexpr (PAIR) {
+            if constexpr (CARRY) {
+                if (q % 2 == 0) gather_blocks<0>(blk[q / 2], q / 2, sm, sc, sp);
+                if (q % 2 == 0) {
+                    CachedPairAcc<CT, 0> A{blk[q / 2]};
+                    pw_point<AR, false, true, false>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2]);
+                } else {
+                    CachedPairAcc<CT, 1> A{blk[q / 2]};
+                    pw_point<AR, false, false, true>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2]);
+                    keep_blocks<0>(blk[q / 2], q / 2);
+                }
+            } else if constexpr (PAIR) {
                 const CT *m[3], *cc[3], *pp[3];
 #pragma unroll
                 for (int f = 0; f < 3; ++f) {
@@ -544,6 +647,11 @@ struct MarchTile {
             }
             put_from(a, 0);
             put_from(b, 1);
+        }
+        if constexpr (CARRY) {
+            __syncthreads();
+#pragma unroll
+            for (int pq = 0; pq < PPT / 2; ++pq) prime_blocks<0>(pq);
         }
         if constexpr (NZ > 0) {
             for (int i = i_begin;; i += UNROLL) {
