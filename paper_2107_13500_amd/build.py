@@ -3,8 +3,10 @@
     python -m paper_2107_13500_amd.build
 
 Compiles every source under ``csrc/`` into one shared library next to this
-file.  Flags: ``-O3``; packed FP32 instructions disabled (hand-written code
-never uses them and the compiler must not form them either); no fast-math.
+file.  Flags: ``-O3``; fused multiply-add formed only within a source
+expression (``-ffp-contract=on``); packed FP32 instructions disabled
+(hand-written code never uses them and the compiler must not form them
+either); no fast-math.
 """
 from __future__ import annotations
 
@@ -28,6 +30,10 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
+    # fuse a*b + c only within one source expression: the rounding then
+    # depends on the source alone, not on the code around it, so every
+    # kernel variant that shares the per-point code rounds identically
+    "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
     "-I", INCLUDE,

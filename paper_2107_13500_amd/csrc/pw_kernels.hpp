@@ -349,12 +349,14 @@ struct MarchTile {
     // plane).  FP64 pairs are single 16-byte reads with immediate offsets.
     static constexpr bool BASES = PAIR && sizeof(CT) == 4;
     int pbo[BASES ? PPT / 2 : 1][3 * NSLOT];
-    // CARRY (converting storage with FP32 compute): blocks read at plane i as
+    // CARRY (with the branch-free data movement): blocks read at plane i as
     // "this plane" or "next plane" are kept in registers and reused at plane
     // i+1 as "previous plane" or "this plane", so a pair reads 17 of its 27
     // blocks from LDS instead of all of them.  cm: blocks for di = -1, c0:
-    // blocks for di = 0, both indexed by pair_carry_key.
-    static constexpr bool CARRY = BASES && EXACT;
+    // blocks for di = 0, both indexed by pair_carry_key.  (FP32 storage,
+    // bound by HBM, measured 4% slower with it: the carried registers cost a
+    // resident workgroup per CU.)
+    static constexpr bool CARRY = PAIR && EXACT;
     using V2 = typename vec2_of<CT>::type;
     V2 cm[CARRY ? PPT / 2 : 1][27];
     V2 c0[CARRY ? PPT / 2 : 1][27];
@@ -471,6 +473,12 @@ struct MarchTile {
         }
     }
 
+    // LDS address of field F of ring slot `slot` at pair pq's window index.
+    __device__ __forceinline__ const CT* block_base(int pq, int slot, int F) const {
+        if constexpr (BASES) return lds + pbo[pq][slot * 3 + F];
+        else return lds + slot * slot_elems() + F * WPAD + li[2 * pq];
+    }
+
     // CARRY: this step's blocks of pair pq, from the carried registers where
     // the previous step read them, else from LDS (slots sm, sc, sp hold planes
     // i-1, i, i+1).  Compile-time loop over all 81 keys; unused keys vanish.
@@ -485,7 +493,7 @@ struct MarchTile {
                     blk[K] = c0[pq][pair_carry_key(F, dj, b)];
                 } else {
                     const int slot = di < 0 ? sm : (di > 0 ? sp : sc);
-                    blk[K] = *reinterpret_cast<const V2*>(lds + pbo[pq][slot * 3 + F] + dj * NZ + b);
+                    blk[K] = *reinterpret_cast<const V2*>(block_base(pq, slot, F) + dj * NZ + b);
                 }
             }
             gather_blocks<K + 1>(blk, pq, sm, sc, sp);
@@ -510,9 +518,9 @@ struct MarchTile {
         if constexpr (K < 27) {
             constexpr int F = K / 9, dj = (K / 3) % 3 - 1, b = (K % 3 - 1) * 2;
             if constexpr (pair_block_used(F, dj, -1, b) && pair_block_used(F, dj, 0, b))
-                cm[pq][K] = *reinterpret_cast<const V2*>(lds + pbo[pq][0 * 3 + F] + dj * NZ + b);
+                cm[pq][K] = *reinterpret_cast<const V2*>(block_base(pq, 0, F) + dj * NZ + b);
             if constexpr (pair_block_used(F, dj, 0, b) && pair_block_used(F, dj, 1, b))
-                c0[pq][K] = *reinterpret_cast<const V2*>(lds + pbo[pq][1 * 3 + F] + dj * NZ + b);
+                c0[pq][K] = *reinterpret_cast<const V2*>(block_base(pq, 1, F) + dj * NZ + b);
             prime_blocks<K + 1>(pq);
         }
     }
