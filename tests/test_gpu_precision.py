@@ -62,6 +62,34 @@ def test_reduced_storage_error_bounds(storage, shape):
         assert e_orig <= ORIG_BOUND[storage], "%s error vs FP64 oracle %.3e" % (name, e_orig)
 
 
+TILINGS = [{"variant": B.VARIANT_MARCH, "chunk": 256, "seg": 1}, {"variant": B.VARIANT_MARCH, "chunk": 512, "seg": 3},
+           {"variant": B.VARIANT_MARCH, "chunk": 1024, "seg": 2}, {"variant": B.VARIANT_MARCH, "chunk": 1024, "seg": 64},
+           {"variant": B.VARIANT_DIRECT}]
+
+
+@pytest.mark.parametrize("storage", [B.F32, B.BF16, B.I16, B.I32], ids=["f32", "bf16", "i16", "i32"])
+@pytest.mark.parametrize("shape", [(37, 29, 64), (20, 9, 96), (13, 6, 128), (7, 13, 72), (5, 3, 30)],
+                         ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("tuning", TILINGS, ids=["m256s1", "m512s3", "m1024s2", "m1024s64", "direct"])
+def test_reduced_storage_tilings(storage, shape, tuning):
+    """Every tiling (one or two pairs of levels per thread, single points,
+    one-plane segments, ragged last chunks, run-time heights) within the
+    arithmetic bound against the oracle on the dequantised inputs."""
+    p = inputs.make_problem(*shape, seed=2300 + shape[0] + shape[2])
+    got, deq, out_scales = run_storage(p, storage, tuning)
+    c = p.coeffs
+    ref_deq = oracle.advect(*deq, c.tcx, c.tcy, *c.arrays())
+    for name, g, rd, os_ in zip(("su", "sv", "sw"), got, ref_deq, out_scales):
+        gi = g[1:-1, 1:-1]
+        assert np.all(gi[:, :, 0] == 0.0)
+        e = max_rel(gi, rd[1:-1, 1:-1])
+        if storage in FIXED:
+            bound = 0.5 / (os_ * np.max(np.abs(rd[1:-1, 1:-1]))) + (1e-12 if storage == B.I32 else 2e-6)
+        else:
+            bound = UNIT_ROUNDOFF[storage] + 2e-6
+        assert e <= bound, "%s %s %s: %.3e > %.3e" % (B.DTYPE_NAMES[storage], tuning, name, e, bound)
+
+
 def test_fp32_difference_first_beats_naive_fp32_on_cancelling_fields():
     """u = 50 + N(0, 0.01), v = 20 + N(0, 0.01): every flux difference cancels
     ~10^3-fold.  Naive FP32 (the staggering rule evaluated in np.float32) loses
