@@ -377,6 +377,10 @@ def streaming_leg(sizes, log, chunks=(32, 64, 128), reps=3):
         log("streaming", name, rec)
         out[name] = rec
         del ins, outs
+        import gc
+        gc.collect()
+        if hasattr(torch._C, "_host_emptyCache"):
+            torch._C._host_emptyCache()   # return the cached pinned blocks before the next size
     return out
 
 

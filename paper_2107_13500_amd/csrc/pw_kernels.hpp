@@ -347,7 +347,7 @@ struct MarchTile {
     // it keeps them in registers instead of re-deriving a base for every
     // merged two-address LDS read (each re-derivation is one VALU add per
     // plane).  FP64 pairs are single 16-byte reads with immediate offsets.
-    static constexpr bool BASES = PAIR && sizeof(CT) == 4;
+    static constexpr bool BASES = PAIR && sizeof(CT) == 4 && EXACT;
     int pbo[BASES ? PPT / 2 : 1][3 * NSLOT];
     // CARRY (with the branch-free data movement): blocks read at plane i as
     // "this plane" or "next plane" are kept in registers and reused at plane

@@ -42,6 +42,7 @@ namespace pw {
 // ---------------------------------------------------------------- FP64: as written
 struct ArithF64 {
     using T = double;
+    static constexpr double kCrossScale = 1.0;   // cross_flux returns the flux difference itself
     static constexpr bool kExactZeroFlux = true;   // c2 * 0 * (w3 + w4) leaves the sum unchanged
     static __device__ __forceinline__ double self_flux(double A, double U, double C) {
         return A * (U + A) - C * (U + C);
@@ -66,11 +67,13 @@ struct ArithSplit {
     static constexpr bool kExactZeroFlux = false;
     // A (U + A) - C (U + C) = (A - C) (U + A + C)
     static __device__ __forceinline__ float self_flux(float A, float U, float C) { return (A - C) * ((U + A) + C); }
-    // E F - G H = ((E - G)(F + H) + (E + G)(F - H)) / 2, with F - H = (v1 - v3) + (v2 - v4)
+    // 2 (E F - G H) = (E - G)(F + H) + (E + G)(F - H), with F - H = (v1 - v3) + (v2 - v4);
+    // the factor 1/2 goes into the term's coefficient (kCrossScale), exactly
+    static constexpr float kCrossScale = 0.5f;
     static __device__ __forceinline__ float cross_flux(float E, float v1, float v2, float G, float v3, float v4) {
         const float fph = (v1 + v2) + (v3 + v4);
         const float fmh = (v1 - v3) + (v2 - v4);
-        return 0.5f * __builtin_fmaf(E - G, fph, (E + G) * fmh);
+        return __builtin_fmaf(E - G, fph, (E + G) * fmh);
     }
     // c1 a (w1 + w2) - c2 c (w3 + w4) with e - g = c1 a - c2 c by Kahan's algorithm
     static __device__ __forceinline__ float add_vert(float s, float c1, float a, float w1, float w2, float c2, float c,
@@ -96,6 +99,7 @@ struct ArithSplit {
 // ---------------------------------------------------------------- FP32: Kahan product differences
 struct ArithKahan {
     using T = float;
+    static constexpr float kCrossScale = 1.0f;
     static constexpr bool kExactZeroFlux = true;   // a b - 0 d = RN(a b) exactly
     // a b - c d: w = RN(c d); e = c d - w exactly; RN(RN(a b - w) - e)
     static __device__ __forceinline__ float pdiff(float a, float b, float c, float d) {
@@ -170,11 +174,12 @@ __device__ __forceinline__ void pw_point(const Acc& A, int k, int nz, const Poin
     const CT v_zm = A.template v<-1, 0, 0>();
 
     // su: Listing 1 -- x term, y term, then the vertical term
+    // cross terms: coefficient x kCrossScale (loop-invariant) x cross_flux
     CT s = c.xu * AR::self_flux(u_xm, u0, u_xp);
-    s = s + c.yu * AR::cross_flux(u_ym, v_ym, A.template v<0, -1, 1>(), u_yp, v0, v_xp);
+    s = s + (c.yu * AR::kCrossScale) * AR::cross_flux(u_ym, v_ym, A.template v<0, -1, 1>(), u_yp, v0, v_xp);
     // sv: mirror of su, own-direction (y) term first
     CT t = c.yv * AR::self_flux(v_ym, v0, v_yp);
-    t = t + c.xv * AR::cross_flux(v_xm, u_xm, A.template u<0, 1, -1>(), v_xp, u0, u_yp);
+    t = t + (c.xv * AR::kCrossScale) * AR::cross_flux(v_xm, u_xm, A.template u<0, 1, -1>(), v_xp, u0, u_yp);
 
     const CT w_u_lo = A.template w<-1, 0, 1>();   // w(k-1, j, i+1): lower z face of u
     const CT w_v_lo = A.template w<-1, 1, 0>();   // w(k-1, j+1, i): lower z face of v
@@ -185,8 +190,10 @@ __device__ __forceinline__ void pw_point(const Acc& A, int k, int nz, const Poin
         a = AR::add_vert(s, c.z1u, u_zm, w_zm, w_u_lo, c.z2u, u_zp, w0, w_xp);
         b = AR::add_vert(t, c.z1v, v_zm, w_zm, w_v_lo, c.z2v, v_zp, w0, w_yp);
         // sw: x and y terms with u, v summed over levels k, k+1; then w along z
-        CT q = c.xw * AR::cross_flux(A.template w<0, 0, -1>(), u_xm, A.template u<1, 0, -1>(), w_xp, u0, u_zp);
-        q = q + c.yw * AR::cross_flux(A.template w<0, -1, 0>(), v_ym, A.template v<1, -1, 0>(), w_yp, v0, v_zp);
+        CT q = (c.xw * AR::kCrossScale) *
+               AR::cross_flux(A.template w<0, 0, -1>(), u_xm, A.template u<1, 0, -1>(), w_xp, u0, u_zp);
+        q = q + (c.yw * AR::kCrossScale) *
+                    AR::cross_flux(A.template w<0, -1, 0>(), v_ym, A.template v<1, -1, 0>(), w_yp, v0, v_zp);
         r = AR::add_vself(q, c.z1w, w_zm, w0, c.z2w, w_zp);
     };
     // column top: su and sv without their upper vertical flux (Sec. III)
