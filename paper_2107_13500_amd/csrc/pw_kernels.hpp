@@ -342,13 +342,6 @@ struct MarchTile {
     // The window vectors of all three fields are spread over the workgroup:
     // round r of this thread moves vector t + r NT -- field fsel[r] (-1: none),
     // element pointer gptr[r] into the plane-0 window, LDS offset loff[r].
-    // FP32 compute with pairs: LDS element offset of each (slot, field) at
-    // each pair's window index.  They are made opaque to the compiler once, so
-    // it keeps them in registers instead of re-deriving a base for every
-    // merged two-address LDS read (each re-derivation is one VALU add per
-    // plane).  FP64 pairs are single 16-byte reads with immediate offsets.
-    static constexpr bool BASES = PAIR && sizeof(CT) == 4 && EXACT;
-    int pbo[BASES ? PPT / 2 : 1][3 * NSLOT];
     // CARRY (with the branch-free data movement): blocks read at plane i as
     // "this plane" or "next plane" are kept in registers and reused at plane
     // i+1 as "previous plane" or "this plane", so a pair reads 17 of its 27
@@ -423,17 +416,6 @@ struct MarchTile {
             hx[f] = static_cast<CT>(d.cx[f]);
             hy[f] = static_cast<CT>(d.cy[f]);
         }
-        if constexpr (BASES) {
-#pragma unroll
-            for (int q = 0; q < PPT / 2; ++q) {
-#pragma unroll
-                for (int n = 0; n < 3 * NSLOT; ++n) {
-                    int o = (n / 3) * slot_elems() + (n % 3) * wpad() + li[2 * q];
-                    asm volatile("" : "+v"(o));
-                    pbo[q][n] = o;
-                }
-            }
-        }
     }
 
     // Issue the global loads of the window of plane ip into `dst`.
@@ -475,8 +457,7 @@ struct MarchTile {
 
     // LDS address of field F of ring slot `slot` at pair pq's window index.
     __device__ __forceinline__ const CT* block_base(int pq, int slot, int F) const {
-        if constexpr (BASES) return lds + pbo[pq][slot * 3 + F];
-        else return lds + slot * slot_elems() + F * WPAD + li[2 * pq];
+        return lds + slot * slot_elems() + F * WPAD + li[2 * pq];
     }
 
     // CARRY: this step's blocks of pair pq, from the carried registers where
@@ -551,17 +532,10 @@ struct MarchTile {
                 const CT *m[3], *cc[3], *pp[3];
 #pragma unroll
                 for (int f = 0; f < 3; ++f) {
-                    if constexpr (BASES) {
-                        const int* b = pbo[q / 2];
-                        m[f] = lds + b[sm * 3 + f];
-                        cc[f] = lds + b[sc * 3 + f];
-                        pp[f] = lds + b[sp * 3 + f];
-                    } else {
-                        const int l0 = li[q & ~1];   // the pair's first (even) index
-                        m[f] = lds + sm * se + f * WPAD + l0;
-                        cc[f] = lds + sc * se + f * WPAD + l0;
-                        pp[f] = lds + sp * se + f * WPAD + l0;
-                    }
+                    const int l0 = li[q & ~1];   // the pair's first (even) index
+                    m[f] = lds + sm * se + f * WPAD + l0;
+                    cc[f] = lds + sc * se + f * WPAD + l0;
+                    pp[f] = lds + sp * se + f * WPAD + l0;
                 }
                 // the pair's first level is odd (k = 1 possible, never the
                 // top); the second is even (never k = 1, the top possible)
