@@ -4,10 +4,12 @@
 //
 // The plan flattens every domain's (chunk, segment) tiles into one global
 // tile range (prefix sums in a device table).  A persistent grid sized to the
-// GPU walks that range; each workgroup maps a tile to its domain by binary
-// search and runs exactly the per-tile code of the single-domain march
-// kernel, so each domain's result is bit-identical to a pw_advect call with
-// the same chunk and segment shape.
+// GPU walks that range (each XCD a contiguous share); each workgroup maps a
+// tile to its domain (a binary search, then a forward scan) and runs the
+// per-tile code of the single-domain march kernel.  The per-point arithmetic
+// is the same source, and the library is built with FMA formed only within
+// a source expression, so each domain's result is bit-identical to a
+// pw_advect call with the same chunk and segment shape.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

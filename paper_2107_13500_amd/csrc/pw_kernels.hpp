@@ -42,8 +42,9 @@ struct DomainArgs {
     const double* tzd1;
     const double* tzd2;
     // Per output (su, sv, sw): x and y coefficients and the factor applied to
-    // the per-level vertical coefficients, with the 16-bit storage scales
-    // folded in (all exact powers of two); plain tcx, tcy, 1 otherwise.
+    // the per-level vertical coefficients, with the storage scales of 16-bit
+    // and int32 storage folded in (all exact powers of two); plain tcx, tcy,
+    // 1 otherwise.
     double cx[3], cy[3], cz[3];
     int32_t nx, ny, nz;
     int32_t pad_;
@@ -339,9 +340,6 @@ struct MarchTile {
     bool live[PPT];          // point lies in the chunk (always true when EXACT)
     CT hx[3], hy[3];       // uniform x and y coefficients of su, sv, sw
     CT zc[PPT][6];         // per-level vertical coefficients of each point
-    // The window vectors of all three fields are spread over the workgroup:
-    // round r of this thread moves vector t + r NT -- field fsel[r] (-1: none),
-    // element pointer gptr[r] into the plane-0 window, LDS offset loff[r].
     // CARRY (with the branch-free data movement): blocks read at plane i as
     // "this plane" or "next plane" are kept in registers and reused at plane
     // i+1 as "previous plane" or "this plane", so a pair reads 17 of its 27
@@ -353,6 +351,9 @@ struct MarchTile {
     using V2 = typename vec2_of<CT>::type;
     V2 cm[CARRY ? PPT / 2 : 1][27];
     V2 c0[CARRY ? PPT / 2 : 1][27];
+    // The window vectors of all three fields are spread over the workgroup:
+    // round r of this thread moves vector t + r NT -- field fsel[r] (-1: none),
+    // element pointer gptr[r] into the plane-0 window, LDS offset loff[r].
     int fsel[NVR];
     const char* gptr[NVR];   // field base + window offset; plane ip adds ip * sx elements
     int loff[NVR];

@@ -61,7 +61,7 @@ namespace pw {
 int64_t elem_bytes(int32_t storage);
 int64_t compute_bytes(int32_t storage);
 int64_t march_lds_bytes(int32_t storage, int32_t wpad);
-bool scaled_storage(int32_t storage);   // 16-bit types with per-field scales
+bool scaled_storage(int32_t storage);   // 16-bit and int32 types: per-field scales
 int32_t normalize_shape(const pw_shape& in, pw_shape* out);
 int64_t extent_elems(const pw_shape& s);
 bool march_possible(const pw_shape& s);

@@ -127,7 +127,7 @@ template <> struct arith_of<float> { using type = ArithSplit; };
 template <> struct arith_of<fx32_t> { using type = ArithF64; };
 
 // Coefficients of one point.  Each output's x and y coefficients are uniform
-// over the domain; the vertical pair is per level.  For 16-bit storage the
+// over the domain; the vertical pair is per level.  For scaled storage the
 // per-field power-of-two scales are folded in (term coefficient x out_scale /
 // (scale of its two fields)), so the arithmetic runs on stored values and
 // yields stored outputs; the folding is exact.
