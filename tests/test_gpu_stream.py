@@ -72,6 +72,25 @@ def test_pageable_host_memory_and_fp32_storage():
         assert torch.equal(o[1:-1, 1:-1], dref[1:-1, 1:-1])
 
 
+@pytest.mark.parametrize("storage", [B.BF16, B.I16, B.I32], ids=["bf16", "i16", "i32"])
+def test_scaled_storage_host_domain_matches_device_call(storage):
+    p = inputs.make_problem(30, 11, 64, seed=123)
+    ins_s, outs_s = inputs.storage_scales(p, B.DTYPE_NAMES[storage])
+    sc = B.make_scales(ins_s, outs_s)
+    ins = [B.to_storage(a, storage, s_).pin_memory() for a, s_ in zip((p.u, p.v, p.w), ins_s)]
+    outs = [torch.zeros(p.u.shape, dtype=B.torch_dtype(storage), pin_memory=True) for _ in range(3)]
+    tz = [torch.from_numpy(x).clone() for x in p.coeffs.arrays()]
+    sp = B.StreamPlan(storage, B.shape_of(ins[0]), chunk=8, nbuffers=2)
+    sp.run(*ins, *outs, p.coeffs.tcx, p.coeffs.tcy, *tz, scales=sc)
+    sp.close()
+    dev_in = [t.to(DEV) for t in ins]
+    d = B.DeviceDomain(*dev_in, p.coeffs.tcx, p.coeffs.tcy, *[t.to(DEV) for t in tz], scales=sc)
+    d.run(B.Plan(storage, [B.shape_of(dev_in[0])]))
+    torch.cuda.synchronize()
+    for o, dref in zip(outs, d.outputs):
+        assert torch.equal(o[1:-1, 1:-1], dref.cpu()[1:-1, 1:-1])
+
+
 def test_repeated_calls_reuse_the_plan():
     p = inputs.make_problem(40, 12, 64, seed=7)
     ins, outs, tz = host_arrays(p)
