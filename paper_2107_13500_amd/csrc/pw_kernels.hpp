@@ -351,6 +351,15 @@ struct MarchTile {
     using V2 = typename vec2_of<CT>::type;
     V2 cm[CARRY ? PPT / 2 : 1][27];
     V2 c0[CARRY ? PPT / 2 : 1][27];
+    // ZEND (pairs with the register carry, policies where a zero product is
+    // an exact zero): the column's end points get zero coefficients instead
+    // of selects -- all of them at k = 1, and at the top the upper vertical
+    // coefficients of su and sv and the horizontal ones of sw (tzd1, tzd2 are
+    // zero there already) -- which gives exactly 0 at k = 1, the column-top
+    // forms at k = nz and sw(nz) = 0 for finite inputs.  ph: per-point copies
+    // of the horizontal coefficients xu, yu, yv, xv, xw, yw.
+    static constexpr bool ZEND = CARRY && arith_of<ST>::type::kExactZeroFlux;
+    CT ph[ZEND ? PPT : 1][6];
     // The window vectors of all three fields are spread over the workgroup:
     // round r of this thread moves vector t + r NT -- field fsel[r] (-1: none),
     // element pointer gptr[r] into the plane-0 window, LDS offset loff[r].
@@ -416,6 +425,24 @@ struct MarchTile {
         for (int f = 0; f < 3; ++f) {
             hx[f] = static_cast<CT>(d.cx[f]);
             hy[f] = static_cast<CT>(d.cy[f]);
+        }
+        if constexpr (ZEND) {
+#pragma unroll
+            for (int q = 0; q < PPT; ++q) {
+                const CT h[6] = {hx[0], hy[0], hy[1], hx[1], hx[2], hy[2]};
+                const bool bottom = q % 2 == 0 && kk[q] == 1;   // first level of a pair: odd k
+                const bool top = q % 2 == 1 && kk[q] == n;      // second level: even k
+#pragma unroll
+                for (int e = 0; e < 6; ++e) ph[q][e] = (bottom || (top && e >= 4)) ? CT(0) : h[e];
+                if (bottom) {
+#pragma unroll
+                    for (int e = 0; e < 6; ++e) zc[q][e] = CT(0);
+                }
+                if (top) {
+                    zc[q][1] = CT(0);   // tzc2 of su
+                    zc[q][3] = CT(0);   // tzc2 of sv
+                }
+            }
         }
     }
 
@@ -517,16 +544,19 @@ struct MarchTile {
 #pragma unroll
         for (int q = 0; q < PPT; ++q) {
             const int l = li[q];
-            const PointCoefs<CT> c{hx[0], hy[0], zc[q][0], zc[q][1], hy[1], hx[1], zc[q][2], zc[q][3],
-                                   hx[2], hy[2], zc[q][4], zc[q][5]};
+            const PointCoefs<CT> c = ZEND ? PointCoefs<CT>{ph[q][0], ph[q][1], zc[q][0], zc[q][1],
+                                                           ph[q][2], ph[q][3], zc[q][2], zc[q][3],
+                                                           ph[q][4], ph[q][5], zc[q][4], zc[q][5]}
+                                          : PointCoefs<CT>{hx[0], hy[0], zc[q][0], zc[q][1], hy[1], hx[1],
+                                                           zc[q][2], zc[q][3], hx[2], hy[2], zc[q][4], zc[q][5]};
             if constexpr (CARRY) {
                 if (q % 2 == 0) gather_blocks<0>(blk[q / 2], q / 2, sm, sc, sp);
                 if (q % 2 == 0) {
                     CachedPairAcc<CT, 0> A{blk[q / 2]};
-                    pw_point<AR, false, true, false>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2]);
+                    pw_point<AR, false, !ZEND, false>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2]);
                 } else {
                     CachedPairAcc<CT, 1> A{blk[q / 2]};
-                    pw_point<AR, false, false, true>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2]);
+                    pw_point<AR, false, false, !ZEND>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2]);
                     keep_blocks<0>(blk[q / 2], q / 2);
                 }
             } else if constexpr (PAIR) {
