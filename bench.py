@@ -147,7 +147,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one GPU only (the stencil kernel on one GPU's domain); "
+        print("bench.py: measures one GPU only (the stencil kernel on one GPU's domain); "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 

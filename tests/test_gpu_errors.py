@@ -1,4 +1,4 @@
-"""C-ABI argument checking (GPU machine; every call here is rejected on the host
+"""C-ABI argument checking (needs a GPU; every call here is rejected on the host
 before anything is launched, so no kernel runs with a bad argument)."""
 import ctypes
 
