@@ -351,14 +351,18 @@ struct MarchTile {
     using V2 = typename vec2_of<CT>::type;
     V2 cm[CARRY ? PPT / 2 : 1][27];
     V2 c0[CARRY ? PPT / 2 : 1][27];
-    // ZEND (pairs with the register carry, policies where a zero product is
-    // an exact zero): the column's end points get zero coefficients instead
-    // of selects -- all of them at k = 1, and at the top the upper vertical
-    // coefficients of su and sv and the horizontal ones of sw (tzd1, tzd2 are
-    // zero there already) -- which gives exactly 0 at k = 1, the column-top
-    // forms at k = nz and sw(nz) = 0 for finite inputs.  ph: per-point copies
-    // of the horizontal coefficients xu, yu, yv, xv, xw, yw.
-    static constexpr bool ZEND = CARRY && arith_of<ST>::type::kExactZeroFlux;
+    // ZEND (fixed-point storage with the register carry, policies where a
+    // zero product is an exact zero): the column's end points get zero
+    // coefficients instead of selects -- all of them at k = 1, and at the top
+    // the upper vertical coefficients of su and sv and the horizontal ones of
+    // sw (tzd1, tzd2 are zero there already).  With finite operands that gives
+    // a zero at k = 1, the column-top forms at k = nz and sw(nz) = 0; the zero
+    // may carry either sign, which the integer output does not keep.  Floating
+    // storage keeps the selects: its k = 1 outputs are +0 bit for bit, and no
+    // value above the column top (level 1 of the next column) can reach a
+    // result through 0 x Inf.  ph: per-point copies of the horizontal
+    // coefficients xu, yu, yv, xv, xw, yw.
+    static constexpr bool ZEND = CARRY && arith_of<ST>::type::kExactZeroFlux && is_fixed_point<ST>;
     CT ph[ZEND ? PPT : 1][6];
     // The window vectors of all three fields are spread over the workgroup:
     // round r of this thread moves vector t + r NT -- field fsel[r] (-1: none),

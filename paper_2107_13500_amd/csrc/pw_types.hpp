@@ -28,6 +28,12 @@ template <typename ST> struct compute_of { using type = float; };
 template <> struct compute_of<double> { using type = double; };
 template <> struct compute_of<fx32_t> { using type = double; };
 
+// Fixed-point storage: every stored value is a finite integer, and a zero of
+// either sign rounds to the stored integer 0.
+template <typename ST> inline constexpr bool is_fixed_point = false;
+template <> inline constexpr bool is_fixed_point<fx16_t> = true;
+template <> inline constexpr bool is_fixed_point<fx32_t> = true;
+
 // ---------------------------------------------------------------------------
 // storage -> compute
 // ---------------------------------------------------------------------------

@@ -35,6 +35,25 @@ def device_domain(p: inputs.Problem, storage: int = B.F64, scales=None, sentinel
     return d
 
 
+_BITS = {torch.float64: torch.int64, torch.float32: torch.int32, torch.bfloat16: torch.int16,
+         torch.float16: torch.int16}
+
+
+def same_bits(a: torch.Tensor, b: torch.Tensor) -> bool:
+    """Bit-for-bit equality (torch.equal compares values, so +0 and -0 would pass)."""
+    if a.dtype != b.dtype or a.shape != b.shape:
+        return False
+    if a.dtype in _BITS:
+        a = a.contiguous().view(_BITS[a.dtype])
+        b = b.contiguous().view(_BITS[b.dtype])
+    return torch.equal(a, b)
+
+
+def positive_zeros(x: np.ndarray) -> bool:
+    """Every element is +0.0 (value zero, sign bit clear)."""
+    return bool(np.all(x == 0.0) and not np.any(np.signbit(x)))
+
+
 def max_rel(g: np.ndarray, o: np.ndarray) -> float:
     den = np.max(np.abs(o))
     return float(np.max(np.abs(g - o)) / den) if den > 0 else float(np.max(np.abs(g)))
@@ -53,9 +72,9 @@ def compare_f64(d: B.DeviceDomain, ref, tol: float = F64_TOL, where: str = ""):
     for name, g_t, o in zip(("su", "sv", "sw"), d.outputs, ref):
         g = g_t.cpu().numpy()
         gi, oi = g[1:-1, 1:-1], o[1:-1, 1:-1]
-        assert np.all(gi[:, :, 0] == 0.0), "%s %s: k = 1 must be exactly 0" % (where, name)
+        assert positive_zeros(gi[:, :, 0]), "%s %s: k = 1 must be exactly +0" % (where, name)
         if name == "sw":
-            assert np.all(gi[:, :, -1] == 0.0), "%s: sw(nz) must be exactly 0" % where
+            assert positive_zeros(gi[:, :, -1]), "%s: sw(nz) must be exactly +0" % where
         e = max_rel(gi, oi)
         errs.append(e)
         assert e <= tol, "%s %s: max-norm relative error %.3e > %.1e" % (where, name, e, tol)
