@@ -14,7 +14,15 @@
  *   sw  the same staggering rule for w on z faces: x and y flux terms with u,
  *       v summed across the two levels k, k+1, and a vertical term in w with
  *       tzd1 (lower) and tzd2 (upper); k = 2..nz-1.
- *   Every output is written as 0 at k = 1, and sw at k = nz.
+ *   Every output is written as 0 at k = 1, and sw at k = nz (+0 for the
+ *   floating storage types).
+ *
+ * Inputs are taken to be finite (fixed-point inputs always are).  For FP64,
+ * BF16 and FP16 storage the staged kernels evaluate the column top as the
+ * full form with the upper vertical flux multiplied by an exact zero, so a
+ * non-finite w at level nz of a column or of its x (su) or y (sv) neighbour
+ * makes su(nz) or sv(nz) NaN, although the truncated formula does not read
+ * that value.
  *
  * The paper prints only su; sv and sw follow the staggering that Listing 1's
  * indices imply and the 21 operations per field that Sec. III counts.
