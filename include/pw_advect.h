@@ -41,9 +41,10 @@
  * Storage precision: PW_F64 computes in FP64.  PW_F32, PW_BF16, PW_F16 and
  * PW_I16 store all six arrays in that type and compute in FP32 with every flux
  * difference in a compensated form: FP32 storage subtracts neighbouring values
- * first (exact when they are within a factor of two); the 16-bit types, whose
- * pairwise sums are exact in FP32, use Kahan's fused multiply-add product
- * difference.  The vertical coefficients stay FP64 in memory and are rounded
+ * first (exact when they are within a factor of two); the 16-bit types use
+ * Kahan's fused multiply-add product difference on sums of two stored values,
+ * which FP32 holds exactly for int16, and for BF16 (FP16) whenever the two
+ * magnitudes are within 2^15 (2^12) of each other.  The vertical coefficients stay FP64 in memory and are rounded
  * to FP32 once per thread.  PW_I32 stores 32-bit fixed point and computes in
  * FP64 (every int32 converts exactly).  For the 16-bit types and PW_I32 each
  * field has a power-of-two scale: stored = value * scale.

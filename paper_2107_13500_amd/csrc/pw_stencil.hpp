@@ -23,8 +23,10 @@
 //               result instead of to the two cancelling products; the
 //               coefficient-weighted vertical difference c1 a - c2 c uses
 //               Kahan's fused multiply-add algorithm.
-//   ArithKahan  16-bit storage, FP32 compute: the sums of two stored values
-//               are exact in FP32, and each product difference E F - G H is
+//   ArithKahan  16-bit storage, FP32 compute: the sum of two stored values
+//               is exact in FP32 for int16 (at most 17 bits), and for BF16
+//               (8-bit significand) or FP16 (11-bit) when the two exponents
+//               differ by at most 15 or 12; each product difference E F - G H is
 //               evaluated by Kahan's FMA algorithm (error <= 2 ulp of the
 //               result; Jeannerod, Louvet, Muller, Math. Comp. 82 (2013)); the
 //               self term uses the exact factorisation (A - C)(U + A + C).
