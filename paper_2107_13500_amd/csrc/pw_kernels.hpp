@@ -366,9 +366,11 @@ struct MarchTile {
     CT ph[ZEND ? PPT : 1][6];
     // The window vectors of all three fields are spread over the workgroup:
     // round r of this thread moves vector t + r NT -- field fsel[r] (-1: none),
-    // element pointer gptr[r] into the plane-0 window, LDS offset loff[r].
+    // element pointer gp[r] into the window of the next plane to load, LDS
+    // offset loff[r].  Planes are loaded in order, so each load advances gp
+    // by one plane (a 64-bit add of a uniform stride instead of a multiply).
     int fsel[NVR];
-    const char* gptr[NVR];   // field base + window offset; plane ip adds ip * sx elements
+    const char* gp[NVR];
     int loff[NVR];
     // DIST planes in flight: plane p lives in register set (p - i_begin + 1) % DIST
     static_assert(DIST == 2 || DIST == 3, "two or three planes in flight");
@@ -400,7 +402,7 @@ struct MarchTile {
             const int q = (v - (f < 0 ? 0 : f) * nvec) * VW;
             fsel[r] = f;
             const ST* base = static_cast<const ST*>(f == 0 ? d.u : (f == 1 ? d.v : d.w));
-            gptr[r] = reinterpret_cast<const char*>(base + (wb + q));
+            gp[r] = reinterpret_cast<const char*>(base + (wb + q));   // plane 0
             loff[r] = (f < 0 ? 0 : f) * wpad() + q;
         }
 #pragma unroll
@@ -450,12 +452,19 @@ struct MarchTile {
         }
     }
 
-    // Issue the global loads of the window of plane ip into `dst`.
-    __device__ __forceinline__ void load_into(Raw* dst, int64_t ip) {
-        const int64_t po = ip * d.sx * (int64_t)sizeof(ST);   // uniform byte offset of the plane
+    // Move the load pointers to plane ip.
+    __device__ __forceinline__ void seek(int64_t ip) {
+        const int64_t po = ip * d.sx * (int64_t)sizeof(ST);
+#pragma unroll
+        for (int r = 0; r < NVR; ++r) gp[r] += po;
+    }
+    // Issue the global loads of the window of the next plane into `dst`.
+    __device__ __forceinline__ void load_next(Raw* dst) {
+        const int64_t ps = d.sx * (int64_t)sizeof(ST);   // uniform plane stride in bytes
 #pragma unroll
         for (int r = 0; r < NVR; ++r) {
-            if (EXACT || fsel[r] >= 0) dst[r] = *reinterpret_cast<const Raw*>(gptr[r] + po);
+            if (EXACT || fsel[r] >= 0) dst[r] = *reinterpret_cast<const Raw*>(gp[r]);
+            gp[r] += ps;
         }
     }
 
@@ -471,8 +480,20 @@ struct MarchTile {
                 } cv;
                 cv.raw = src[r];
                 CT out[VW];
+                if constexpr (std::is_same<ST, bf16_t>::value && VEC) {
+                    // a BF16 value is the upper half of its FP32 value: per
+                    // 32-bit word, shift the low element up, mask the high one
+                    uint32_t wd[sizeof(Raw) / 4];
+                    __builtin_memcpy(wd, &cv.raw, sizeof(Raw));
 #pragma unroll
-                for (int n = 0; n < VW; ++n) out[n] = to_compute(cv.e[n]);
+                    for (int n = 0; n < VW / 2; ++n) {
+                        out[2 * n] = __uint_as_float(wd[n] << 16);
+                        out[2 * n + 1] = __uint_as_float(wd[n] & 0xffff0000u);
+                    }
+                } else {
+#pragma unroll
+                    for (int n = 0; n < VW; ++n) out[n] = to_compute(cv.e[n]);
+                }
                 CT* dst = slot + loff[r];
                 if constexpr (VW * sizeof(CT) >= 16) {
 #pragma unroll
@@ -616,7 +637,7 @@ struct MarchTile {
     __device__ __forceinline__ void step(int i, int i_end, int sm, int sc, int sp) {
         put_from(st[SET], sp);
         __syncthreads();
-        if (i + 1 + DIST <= i_end + 1) load_into(st[SET], (int64_t)(i + 1 + DIST));
+        if (i + 1 + DIST <= i_end + 1) load_next(st[SET]);   // plane i + 1 + DIST
         compute(i, sm, sc, sp);
         if constexpr (NSLOT == 3) __syncthreads();
     }
@@ -654,13 +675,18 @@ struct MarchTile {
         // the first planes are requested together, so a tile's start waits
         // for one memory latency, not several
         {
+            // planes i_begin - 1, i_begin, i_begin + 1 (<= nx + 1, always
+            // there), then up to i_begin + DIST; the steps continue in order
+            // with plane i + 1 + DIST, and once one plane lies past i_end + 1
+            // every later one does too
             Raw a[NVR], b[NVR];
-            load_into(a, (int64_t)(i_begin - 1));
-            load_into(b, (int64_t)i_begin);
-            load_into(st[0], (int64_t)(i_begin + 1));   // plane i_begin + 1 <= nx + 1 always exists
+            seek((int64_t)(i_begin - 1));
+            load_next(a);
+            load_next(b);
+            load_next(st[0]);
 #pragma unroll
             for (int q = 1; q < DIST; ++q) {
-                if (i_begin + 1 + q <= i_end + 1) load_into(st[q], (int64_t)(i_begin + 1 + q));
+                if (i_begin + 1 + q <= i_end + 1) load_next(st[q]);
             }
             put_from(a, 0);
             put_from(b, 1);
