@@ -117,12 +117,14 @@ __device__ __forceinline__ void store_pair(ST* p, typename compute_of<ST>::type 
         __builtin_memcpy(&bits, &h, 4);
         __builtin_nontemporal_store(bits, reinterpret_cast<uint32_t*>(p));
     } else {
-        ST ya = from_compute<ST>(a), yb = from_compute<ST>(b);
-        uint16_t ba, bb;
-        __builtin_memcpy(&ba, &ya, 2);
-        __builtin_memcpy(&bb, &yb, 2);
-        __builtin_nontemporal_store(static_cast<uint32_t>(ba) | (static_cast<uint32_t>(bb) << 16),
-                                    reinterpret_cast<uint32_t*>(p));
+        // int16: from_compute's rounding and clamp, then one packing
+        // conversion of the two in-range integers (v_cvt_pk_i16_i32)
+        static_assert(std::is_same<ST, fx16_t>::value, "int16 fixed point");
+        typedef short i16x2 __attribute__((ext_vector_type(2)));
+        const i16x2 h = __builtin_amdgcn_cvt_pk_i16(fx16_round(a), fx16_round(b));
+        uint32_t bits;
+        __builtin_memcpy(&bits, &h, 4);
+        __builtin_nontemporal_store(bits, reinterpret_cast<uint32_t*>(p));
     }
 }
 

@@ -54,10 +54,12 @@ template <> __device__ __forceinline__ double from_compute<double>(double x) { r
 template <> __device__ __forceinline__ float from_compute<float>(float x) { return x; }
 template <> __device__ __forceinline__ f16_t from_compute<f16_t>(float x) { return static_cast<f16_t>(x); }
 // round to nearest even, saturate to the int16 range (NaN becomes -32768)
+__device__ __forceinline__ int fx16_round(float x) {
+    return static_cast<int>(__builtin_fminf(__builtin_fmaxf(__builtin_rintf(x), -32768.0f), 32767.0f));
+}
 template <> __device__ __forceinline__ fx16_t from_compute<fx16_t>(float x) {
-    const float r = __builtin_fminf(__builtin_fmaxf(__builtin_rintf(x), -32768.0f), 32767.0f);
     fx16_t y;
-    y.v = static_cast<int16_t>(static_cast<int>(r));
+    y.v = static_cast<int16_t>(fx16_round(x));
     return y;
 }
 // round to nearest even, saturate to the int32 range (NaN becomes -2^31)

@@ -94,6 +94,41 @@ def test_reduced_storage_tilings(storage, shape, tuning):
         assert e <= bound, "%s %s %s: %.3e > %.3e" % (B.DTYPE_NAMES[storage], tuning, name, e, bound)
 
 
+
+@pytest.mark.parametrize("storage", [B.I16, B.I32], ids=["i16", "i32"])
+@pytest.mark.parametrize("tuning", [{"variant": B.VARIANT_MARCH, "chunk": 512, "seg": 4}, {"variant": B.VARIANT_DIRECT}],
+                         ids=["march", "direct"])
+def test_fixed_point_outputs_round_and_saturate(storage, tuning):
+    """Output scales 64 times too large for the type: results beyond the range
+    store its limits, the others round to the nearest integer."""
+    p = inputs.make_problem(21, 11, 64, seed=4321)
+    ins, outs = inputs.storage_scales(p, B.DTYPE_NAMES[storage])
+    outs = [s * 64.0 for s in outs]
+    fields = [B.to_storage(a, storage, s, DEV) for a, s in zip((p.u, p.v, p.w), ins)]
+    tz = [torch.from_numpy(x).to(DEV) for x in p.coeffs.arrays()]
+    d = B.DeviceDomain(*fields, p.coeffs.tcx, p.coeffs.tcy, *tz, scales=B.make_scales(ins, outs))
+    d.run(B.Plan(storage, [B.shape_of(fields[0])], tuning))
+    torch.cuda.synchronize()
+    c = p.coeffs
+    deq = [B.from_storage(f, storage, s) for f, s in zip(fields, ins)]
+    ref = oracle.advect(*deq, c.tcx, c.tcy, *c.arrays())
+    lo, hi = B.FIXED_RANGE[storage]
+    for name, o, r, s in zip(("su", "sv", "sw"), d.outputs, ref, outs):
+        g = o.cpu().numpy()[1:-1, 1:-1].astype(np.int64)
+        x = r[1:-1, 1:-1] * s
+        # half a unit for the rounding, plus the compute type's error relative
+        # to the largest result; results farther than that from a limit must
+        # saturate or stay in range
+        tol = 0.5 + (1e-12 if storage == B.I32 else 2e-6) * np.max(np.abs(x))
+        over, under = x > hi + tol, x < lo - tol
+        assert over.any() and under.any(), "%s: the scale must push results out of range" % name
+        assert np.all(g[over] == hi) and np.all(g[under] == lo), "%s: saturation" % name
+        inside = (x > lo + tol) & (x < hi - tol)
+        assert inside.any()
+        err = np.max(np.abs(g[inside] - x[inside]))
+        say(B.DTYPE_NAMES[storage], tuning, name, "in-range error %.3f units (bound %.3f)" % (err, tol))
+        assert err <= tol, "%s: %.3f > %.3f" % (name, err, tol)
+
 def test_fp32_difference_first_beats_naive_fp32_on_cancelling_fields():
     """u = 50 + N(0, 0.01), v = 20 + N(0, 0.01): every flux difference cancels
     ~10^3-fold.  Naive FP32 (the staggering rule evaluated in np.float32) loses
