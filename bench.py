@@ -6,8 +6,9 @@
 One step is one call of the whole stencil (su, sv and sw of every point of
 one domain) on the 2048 x 2048 x 64 FP64 grid, inputs resident in HBM.  Rank
 0 prints one JSON line: Gpoints/s, the HBM roofline of the kernel (algorithmic
-bytes / measured kernel time against the 8 TB/s peak), the CPU oracle timed on
-the host cores, the storage-precision variants (FP32, BF16, FP16 and int16
+bytes / measured kernel time against the 8 TB/s peak), the median and minimum
+of single launches, the CPU oracle timed on the host cores (all usable cores up
+to 16, and one thread), the storage-precision variants (FP32, BF16, FP16 and int16
 with FP32 compensated compute; int32 fixed point with FP64 compute) with their
 error against the FP64 oracle, the batched many-subdomain form, board power
 and host-resident (PCIe-inclusive) runs.
@@ -67,6 +68,20 @@ def time_steps(fn, steps, warmup, stream):
     return e0.elapsed_time(e1) / steps
 
 
+def per_launch(fn, n, stream):
+    """Median and minimum of n launches, each bracketed by its own pair of
+    events on the launch stream (run after the timed region, not part of it)."""
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    t = sorted(a.elapsed_time(b) for a, b in evs)
+    return {"median": round(t[n // 2], 5), "min": round(t[0], 5), "launches": n}
+
+
 def settle(fn, stream, seconds=0.3):
     """Run fn back to back for about `seconds` (untimed) so the GPU leaves its
     idle clocks after host-side work such as input generation."""
@@ -110,8 +125,23 @@ def measured_traffic(kernel_key, chunk, seg):
     return rec.get("traffic_bytes")
 
 
-def cpu_baseline(p, threads):
-    """The FP64 oracle on the same grid, timed on the host; returns (record, reference outputs)."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(p, threads, slab=256):
+    """The FP64 oracle on the same grid, timed on the host with `threads`
+    OpenMP threads, and on one thread over an x-slab of the grid (the same
+    per-point work, so the rate carries over); returns (record, reference
+    outputs of the full grid)."""
+    import numpy as np
     import oracle
     reps = 6   # about 1 s of wall time (10-20 s of CPU time) on 16 host threads
     t0 = time.perf_counter()
@@ -119,9 +149,22 @@ def cpu_baseline(p, threads):
     for _ in range(reps):
         ref = oracle.advect_problem(p, threads=threads)
     dt = (time.perf_counter() - t0) / reps
+    # one thread: the first `slab` interior x-planes with their halo planes
+    c = p.coeffs
+    sl = [np.ascontiguousarray(a[:slab + 2]) for a in (p.u, p.v, p.w)]
+    reps1 = 3
+    t0 = time.perf_counter()
+    for _ in range(reps1):
+        oracle.advect(*sl, c.tcx, c.tcy, *c.arrays(), threads=1)
+    dt1 = (time.perf_counter() - t0) / reps1
+    pts1 = slab * p.ny * p.nz
     rec = {"value": p.npoints / dt / 1e9, "unit": "Gpoints/s", "cores": threads, "kind": "oracle",
            "sample": "full %dx%dx%d grid, %d oracle calls (plain C FP64, no FMA), %d OpenMP threads, "
-                     "%.2f s per call" % (p.nx, p.ny, p.nz, reps, threads, dt)}
+                     "%.2f s per call" % (p.nx, p.ny, p.nz, reps, threads, dt),
+           "single_thread": {"value": pts1 / dt1 / 1e9, "unit": "Gpoints/s",
+                             "sample": "x-slab of %d planes (%dx%dx%d), %d oracle calls on 1 thread, %.2f s per call"
+                                       % (slab, slab, p.ny, p.nz, reps1, dt1)},
+           "cpu_model": cpu_model(), "host_cpus_usable": len(os.sched_getaffinity(0))}
     return rec, ref
 
 
@@ -188,6 +231,8 @@ def main():
     abytes = metrics.algorithmic_bytes(nx, ny, nz, 8)
     achieved = abytes / (ms * 1e-3) / 1e9
     log("FP64: %.4f ms/step, %.2f Gpts/s, %.1f GB/s algorithmic" % (ms, gpts, achieved))
+    launches = per_launch(lambda: d64.run(plan, stream), max(args.steps, 5), stream)
+    log("FP64 per launch", launches)
 
     result = {
         "metric": METRIC, "value": round(gpts, 3), "unit": "Gpoints/s", "n_gpus": 1,
@@ -203,6 +248,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "algorithmic_bytes_per_launch": abytes},
         "paper_equivalent_gflops": round(metrics.paper_equivalent_gflops(gpts * 1e9, nz), 1),
+        "per_launch_ms": launches,
     }
 
     if info["variant"] == B.VARIANT_MARCH:
@@ -261,6 +307,7 @@ def main():
         usable = len(os.sched_getaffinity(0))
         threads = args.cpu_threads or min(usable, 16)
         rec, ref = cpu_baseline(p, threads)
+        rec["gpu_over_oracle"] = round(gpts / rec["value"], 1)
         result["cpu_baseline"] = rec
         log("oracle: %.3f Gpts/s on %d threads" % (rec["value"], threads))
         torch.cuda.synchronize()
