@@ -54,18 +54,22 @@ bool scaled_storage(int32_t storage) {
 int32_t normalize_shape(const pw_shape& in, pw_shape* out) {
     pw_shape s = in;
     if (s.nx < 1 || s.ny < 1 || s.nz < 2 || s.reserved != 0) return PW_ERR_INVALID_ARG;
-    if (s.sy == 0) s.sy = s.nz;
-    if (s.sx == 0) s.sx = (int64_t)(s.ny + 2) * s.sy;
-    if (s.sy < s.nz || s.sx < (int64_t)(s.ny + 2) * s.sy) return PW_ERR_INVALID_ARG;
-    // 32-bit in-plane indexing in the kernels
-    if ((int64_t)(s.ny + 2) * s.nz >= (int64_t(1) << 31)) return PW_ERR_INVALID_ARG;
-    if ((int64_t)s.ny * s.nz >= (int64_t(1) << 31)) return PW_ERR_INVALID_ARG;
+    const int64_t nx = s.nx, ny = s.ny, nz = s.nz;
+    // 32-bit in-plane indexing in the kernels; plane indices up to nx + 1
+    if ((ny + 2) * nz >= (int64_t(1) << 31) || nx + 2 >= (int64_t(1) << 31)) return PW_ERR_INVALID_ARG;
+    // strides: every element offset stays below 2^48 (far beyond any device
+    // memory), so element and byte offsets never overflow 64 bits
+    constexpr int64_t kMaxElems = int64_t(1) << 48;
+    if (s.sy == 0) s.sy = nz;
+    if (s.sy < nz || s.sy > kMaxElems / (ny + 2)) return PW_ERR_INVALID_ARG;
+    if (s.sx == 0) s.sx = (ny + 2) * s.sy;
+    if (s.sx < (ny + 2) * s.sy || s.sx > kMaxElems / (nx + 2)) return PW_ERR_INVALID_ARG;
     *out = s;
     return PW_OK;
 }
 
 int64_t extent_elems(const pw_shape& s) {
-    return (int64_t)(s.nz - 1) + (int64_t)(s.ny + 1) * s.sy + (int64_t)(s.nx + 1) * s.sx + 1;
+    return (int64_t)(s.nz - 1) + ((int64_t)s.ny + 1) * s.sy + ((int64_t)s.nx + 1) * s.sx + 1;
 }
 
 bool march_possible(const pw_shape& s) {

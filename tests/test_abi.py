@@ -51,6 +51,24 @@ def test_status_strings_without_a_device():
     assert lib.pw_last_hip_error() == 0
 
 
+def test_plan_rejects_out_of_range_shapes_without_a_device():
+    """Shape checks run on the host before any device call: strides or
+    extents whose offsets would overflow, and 32-bit index limits."""
+    lib = B.lib()
+    big = 1 << 62
+    bad = [B.PwShape(4, 4, 8, 0, big, 0),                 # sy: (ny + 2) sy would overflow
+           B.PwShape(4, 4, 8, 0, 0, big),                 # sx: offsets beyond 2^48 elements
+           B.PwShape(4, 2 ** 31 - 1, 8, 0, 0, 0),         # ny + 2 overflows 32 bits
+           B.PwShape(2 ** 31 - 1, 4, 8, 0, 0, 0),         # plane index nx + 1 beyond 32 bits
+           B.PwShape(4, 2 ** 26, 64, 0, 0, 0),            # (ny + 2) nz >= 2^31
+           B.PwShape(4, 4, 8, 0, -8, 0), B.PwShape(4, 4, 8, 0, 0, -1)]
+    for s in bad:
+        h = ctypes.c_void_p()
+        assert lib.pw_advect_plan(ctypes.byref(h), B.F64, (B.PwShape * 1)(s), 1, None) == -1, \
+            (s.nx, s.ny, s.nz, s.sy, s.sx)
+        assert not h.value
+
+
 PROBE = r"""
 #include <stddef.h>
 #include <stdio.h>
