@@ -272,8 +272,9 @@ int32_t pw_stream_plan_destroy(pw_stream_plan *plan);
    same data).  All pointers are HOST pointers; pinned memory (hipHostMalloc)
    lets the copies run asynchronously and overlap.  Each array must span the
    domain's extent; the output halo columns are never written.  Blocks until
-   the outputs are on the host.  Returns PW_ERR_ALIAS if an output overlaps an
-   input. */
+   the outputs are on the host; an error return, too, comes only after every
+   copy and kernel the call queued has finished, so the host buffers may be
+   released at once.  Returns PW_ERR_ALIAS if an output overlaps an input. */
 int32_t pw_advect_host(pw_stream_plan *plan,
                        const void *h_u, const void *h_v, const void *h_w,
                        void *h_su, void *h_sv, void *h_sw,

@@ -69,6 +69,15 @@ int32_t hip_status(hipError_t e) {
     return pw::report_hip(e);
 }
 
+// An error return first waits for the copies and kernels already queued on
+// the plan's streams: they reference the caller's host buffers, which the
+// caller may release once the call has returned.
+int32_t fail(pw_stream_plan* p, int32_t rc) {
+    for (hipStream_t s : {p->s_in[0], p->s_in[1], p->s_in[2], p->s_run, p->s_out[0], p->s_out[1], p->s_out[2]})
+        if (s) (void)hipStreamSynchronize(s);
+    return rc;
+}
+
 }  // namespace
 
 extern "C" {
@@ -175,7 +184,7 @@ int32_t pw_advect_host(pw_stream_plan* p, const void* h_u, const void* h_v, cons
     for (int q = 0; q < 4 && e == hipSuccess; ++q)
         e = hipMemcpyAsync(p->coef + q * s.nz, hc[q], sizeof(double) * s.nz, hipMemcpyHostToDevice, p->s_run);
     if (e == hipSuccess) e = hipStreamSynchronize(p->s_run);
-    if (e != hipSuccess) return hip_status(e);
+    if (e != hipSuccess) return fail(p, hip_status(e));
     const double* dc[4] = {p->coef, p->coef + s.nz, p->coef + 2 * s.nz, p->coef + 3 * s.nz};
     // interior columns of one plane: j = 1..ny, contiguous from offset sy
     const size_t row_bytes = (size_t)s.ny * s.sy * eb;
@@ -186,15 +195,15 @@ int32_t pw_advect_host(pw_stream_plan* p, const void* h_u, const void* h_v, cons
         const size_t fb = (size_t)(s.nx + 2) * pb;
         for (int f = 0; f < 3 && e == hipSuccess; ++f)
             e = hipMemcpyAsync(dev + f * fb, hin[f], (size_t)ext, hipMemcpyHostToDevice, p->s_run);
-        if (e != hipSuccess) return hip_status(e);
+        if (e != hipSuccess) return fail(p, hip_status(e));
         int32_t rc = pw_advect(p->plan_bulk, dev, dev + fb, dev + 2 * fb, dev + 3 * fb, dev + 4 * fb, dev + 5 * fb,
                                tcx, tcy, dc[0], dc[1], dc[2], dc[3], scales, p->s_run);
-        if (rc != PW_OK) return rc;
+        if (rc != PW_OK) return fail(p, rc);
         for (int f = 0; f < 3 && e == hipSuccess; ++f)
             e = hipMemcpy2DAsync(hout[f] + pb + row_off, pb, dev + (3 + f) * fb + pb + row_off, pb, row_bytes,
                                  s.nx, hipMemcpyDeviceToHost, p->s_run);
         if (e == hipSuccess) e = hipStreamSynchronize(p->s_run);
-        return e == hipSuccess ? PW_OK : hip_status(e);
+        return e == hipSuccess ? PW_OK : fail(p, hip_status(e));
     }
 
     const int32_t nchunks = (s.nx + p->chunk - 1) / p->chunk;
@@ -220,11 +229,11 @@ int32_t pw_advect_host(pw_stream_plan* p, const void* h_u, const void* h_v, cons
             e = hipStreamWaitEvent(p->s_run, p->ev_in[3 * b + f], 0);
             if (e == hipSuccess && c >= p->nbuf) e = hipStreamWaitEvent(p->s_run, p->ev_out[3 * b + f], 0);
         }
-        if (e != hipSuccess) return hip_status(e);
+        if (e != hipSuccess) return fail(p, hip_status(e));
         const pw_plan* pl = n == p->chunk ? p->plan_full : p->plan_tail;
         int32_t rc = pw_advect(pl, din, din + fin, din + 2 * fin, dout, dout + fin, dout + 2 * fin, tcx, tcy, dc[0],
                                dc[1], dc[2], dc[3], scales, p->s_run);
-        if (rc != PW_OK) return rc;
+        if (rc != PW_OK) return fail(p, rc);
         e = hipEventRecord(p->ev_run[b], p->s_run);
         // outputs: interior columns of planes i0..i0+n-1
         for (int f = 0; f < 3 && e == hipSuccess; ++f) {
@@ -235,10 +244,10 @@ int32_t pw_advect_host(pw_stream_plan* p, const void* h_u, const void* h_v, cons
                                      row_bytes, n, hipMemcpyDeviceToHost, so);
             if (e == hipSuccess) e = hipEventRecord(p->ev_out[3 * b + f], so);
         }
-        if (e != hipSuccess) return hip_status(e);
+        if (e != hipSuccess) return fail(p, hip_status(e));
     }
     for (int f = 0; f < kCopyStreams && e == hipSuccess; ++f) e = hipStreamSynchronize(p->s_out[f]);
-    return e == hipSuccess ? PW_OK : hip_status(e);
+    return e == hipSuccess ? PW_OK : fail(p, hip_status(e));
 }
 
 }  // extern "C"
