@@ -93,20 +93,24 @@ def settle(fn, stream, seconds=0.3):
         torch.cuda.synchronize()
 
 
-def copy_ceiling(gbytes, steps, warmup, dev, stream, nstreams=1, workgroups=65536):
+def copy_ceiling(gbytes, steps, warmup, dev, stream, nstreams=1, grids=(16384, 32768, 65536)):
     """Read+write bandwidth of the library's plain streaming copy (pw_probe_copy)
-    over `nstreams` buffers of `gbytes` GB each."""
+    over `nstreams` buffers of `gbytes` GB each: the best over several grid
+    sizes, since the copy's rate depends on how its concurrent requests fall
+    over the HBM channels (about +-10% between grid sizes)."""
     import torch
     from paper_2107_13500_amd import binding as B
     n = int(gbytes * 1e9) // 16 * 16
     src = [torch.ones(n // 8, dtype=torch.float64, device=dev) for _ in range(nstreams)]
     dst = [torch.empty_like(a) for a in src]
-    ms = time_steps(lambda: B.probe_copy(src, dst, n, workgroups, stream), steps, warmup, stream)
+    per = {g: time_steps(lambda: B.probe_copy(src, dst, n, g, stream), steps, warmup, stream) for g in grids}
     moved = 2 * n * nstreams
     del src, dst
     torch.cuda.empty_cache()
-    return {"streams": nstreams, "bytes_per_copy": moved, "ms": round(ms, 5),
-            "gbs": round(moved / (ms * 1e-3) / 1e9, 1)}
+    best = min(per, key=per.get)
+    return {"streams": nstreams, "bytes_per_copy": moved, "ms": round(per[best], 5),
+            "gbs": round(moved / (per[best] * 1e-3) / 1e9, 1), "workgroups": best,
+            "gbs_by_workgroups": {str(g): round(moved / (t * 1e-3) / 1e9, 1) for g, t in per.items()}}
 
 
 def measured_traffic(kernel_key, chunk, seg):
