@@ -10,7 +10,7 @@ from __future__ import annotations
 import ctypes
 import os
 from ctypes import POINTER, c_double, c_float, c_int32, c_int64, c_uint64, c_ulonglong, c_void_p
-from typing import Iterable, List, Optional, Sequence
+from typing import List, Optional, Sequence
 
 LIBRARY = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpwadvect.so")
 

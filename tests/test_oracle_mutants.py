@@ -10,7 +10,6 @@ second evaluation of the same formulas.
 """
 import os
 import subprocess
-import tempfile
 
 import pytest
 
