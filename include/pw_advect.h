@@ -110,7 +110,9 @@ typedef struct pw_shape {
    variant    PW_VARIANT_*.
    chunk      points of the (j, k) plane one workgroup owns in the march
               variant (and in the batched kernel): 256, 512 or 1024.
-   seg        x planes one workgroup marches through (>= 1).
+   seg        x planes one workgroup marches through (>= 1).  In the batched
+              kernel each domain splits its nx planes into ceil(nx / seg)
+              segments of as even a length as possible (at most seg).
    block      threads per workgroup of the direct variant: 64, 128, 256 or 512.
    wg_per_cu  resident workgroups per compute unit of the persistent batched
               launch (1..8; further capped by LDS). */

@@ -30,7 +30,7 @@ struct BatchDomain {
     int32_t nx, ny, nz;
     int32_t nchunks;
     int32_t nseg;
-    int32_t pad_;
+    int32_t seg;          // planes per segment: nx split into nseg even parts
     int64_t sy, sx;
     int64_t tile_begin;   // first global tile of this domain
 };
