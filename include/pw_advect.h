@@ -115,7 +115,10 @@ typedef struct pw_shape {
               segments of as even a length as possible (at most seg).
    block      threads per workgroup of the direct variant: 64, 128, 256 or 512.
    wg_per_cu  resident workgroups per compute unit of the persistent batched
-              launch (1..8; further capped by LDS). */
+              launch (1..8; further capped by LDS), or PW_WG_ONE_PER_TILE:
+              one workgroup per tile instead of a persistent grid, so the
+              hardware hands out the tiles in order (still one launch). */
+#define PW_WG_ONE_PER_TILE (-1)
 typedef struct pw_tuning {
     int32_t variant;
     int32_t chunk;

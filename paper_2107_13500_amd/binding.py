@@ -24,6 +24,7 @@ F64, F32, BF16, F16, I16, I32 = 0, 1, 2, 3, 4, 5
 SCALED = (BF16, F16, I16, I32)
 FIXED_RANGE = {I16: (-32768, 32767), I32: (-2147483648, 2147483647)}
 VARIANT_AUTO, VARIANT_DIRECT, VARIANT_MARCH = 0, 1, 2
+WG_ONE_PER_TILE = -1   # pw_tuning.wg_per_cu: one workgroup per tile instead of a persistent grid
 DTYPE_NAMES = {F64: "f64", F32: "f32", BF16: "bf16", F16: "f16", I16: "i16", I32: "i32"}
 
 

@@ -99,6 +99,8 @@ __global__ __launch_bounds__(NT) void pw_batched_kernel(const BatchDomain* __res
     // contiguous share of the tile range, walked by its own workgroups, so
     // the tiles in flight on one XCD are neighbouring chunks and segments of
     // the same domains and share their halo columns and planes in its L2.
+    // With one workgroup per tile (G == ntiles) every workgroup takes exactly
+    // one tile, in the XCD-contiguous order of the single-domain kernel.
     const int G = (int)gridDim.x;
     const int x = (int)blockIdx.x % kNumXcd;
     const int slot = (int)blockIdx.x / kNumXcd;
@@ -355,7 +357,7 @@ int32_t batched_plan_init(pw_plan* p) {
     const pw_tuning& t = p->tuning;
     const int32_t chunk = t.chunk ? t.chunk : 512;
     if (chunk != 256 && chunk != 512 && chunk != 1024) return PW_ERR_INVALID_ARG;
-    if (t.seg < 0 || t.wg_per_cu < 0 || t.wg_per_cu > 8) return PW_ERR_INVALID_ARG;
+    if (t.seg < 0 || t.wg_per_cu < PW_WG_ONE_PER_TILE || t.wg_per_cu > 8) return PW_ERR_INVALID_ARG;
     int32_t nzmax = 0;
     for (const pw_shape& s : p->shapes) nzmax = std::max(nzmax, s.nz);
 
@@ -409,6 +411,16 @@ int32_t batched_plan_init(pw_plan* p) {
     if (occ > 0) per_cu = std::min<int64_t>(per_cu, occ);
     if (t.wg_per_cu > 0) per_cu = std::min<int64_t>(per_cu, t.wg_per_cu);
     L.workgroups = std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)prop.multiProcessorCount * per_cu));
+    // One workgroup per tile: the kernel's tile loop then runs once per
+    // workgroup, and the hardware dispatches tiles in order as workgroups
+    // retire, so the workgroups on neighbouring chunks stay in step (their
+    // shared halo columns meet in L2) where a persistent grid's fixed
+    // round-robin shares drift apart.  Measured on the 384-domain batch: 2-3%
+    // faster than the best persistent grid for FP64, FP32 and BF16.
+    if (t.wg_per_cu == PW_WG_ONE_PER_TILE) {
+        if (tiles >= (int64_t(1) << 31)) return PW_ERR_UNSUPPORTED;
+        L.workgroups = tiles;
+    }
     L.nchunks = 0;
     L.nseg = 0;
 

@@ -41,8 +41,9 @@ def single_outputs(batch, d, tuning):
 
 
 @pytest.mark.parametrize("tuning", [{"chunk": 256, "seg": 8}, {"chunk": 512, "seg": 64},
-                                    {"chunk": 1024, "seg": 16, "wg_per_cu": 2}],
-                         ids=["c256s8", "c512s64", "c1024s16w2"])
+                                    {"chunk": 1024, "seg": 16, "wg_per_cu": 2},
+                                    {"chunk": 512, "seg": 16, "wg_per_cu": B.WG_ONE_PER_TILE}],
+                         ids=["c256s8", "c512s64", "c1024s16w2", "c512s16-one-per-tile"])
 def test_batched_f64_parity_and_bit_identity(tuning):
     probs = small_problems()
     batch = BT.DeviceBatch(probs, B.F64, DEV)

@@ -42,6 +42,9 @@ def test_plan_rejects_bad_shapes_and_tunings():
     assert plan_status(7, [ok]) == -2                                        # unknown storage
     assert plan_status(B.F64, [ok], {"chunk": 300}) == -1
     assert plan_status(B.F64, [ok], {"variant": 9}) == -2
+    assert plan_status(B.F64, [ok], {"wg_per_cu": -2}) == -1
+    assert plan_status(B.F64, [ok], {"wg_per_cu": 9}) == -1
+    assert plan_status(B.F64, [ok], {"wg_per_cu": B.WG_ONE_PER_TILE}) == 0
     assert plan_status(B.F64, [B.PwShape(4, 4, 8, 0, 10, 0)], {"variant": B.VARIANT_MARCH}) == -2
     assert plan_status(B.F64, [B.PwShape(4, 4, 300, 0, 0, 0)], {"variant": B.VARIANT_MARCH}) == -2
     assert plan_status(B.F64, [ok], {"variant": B.VARIANT_DIRECT, "block": 100}) == -1
