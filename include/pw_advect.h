@@ -152,7 +152,7 @@ typedef struct pw_plan_info {
     int64_t tiles;        /* (chunk, segment) tiles over all domains */
     int64_t lds_bytes;    /* dynamic LDS per workgroup */
     int64_t points;       /* interior grid points over all domains */
-    int64_t batched_workgroups;  /* persistent grid of pw_advect_batched (0 if unavailable) */
+    int64_t batched_workgroups;  /* grid of pw_advect_batched: persistent, or one per tile (0 if unavailable) */
 } pw_plan_info;
 
 /* Create a plan for `ndomains` domains (1 for pw_advect; the batch size for
@@ -218,7 +218,8 @@ typedef struct pw_domain_args {
     pw_scales scales;
 } pw_domain_args;
 
-/* su, sv, sw of all domains of a batched plan in one persistent launch.
+/* su, sv, sw of all domains of a batched plan in one launch (a persistent
+   grid, or one workgroup per tile with wg_per_cu = PW_WG_ONE_PER_TILE).
      plan       plan created with the batch's shapes (ndomains > 1 allowed, 1 too).
      ndomains   must equal the plan's ndomains (PW_ERR_PLAN_MISMATCH).
      d_args     device array of ndomains pw_domain_args.
