@@ -267,12 +267,16 @@ def test_autotune_single_domain_default_space():
     assert sum(1 for _, t in table if t > 0) >= 3
 
 
-def test_full_384_domain_batch_graph():
-    """The 384-subdomain configuration: graph-captured timestep replayed, sampled domains vs oracle."""
+@pytest.mark.parametrize("tuning", [None, {"chunk": 512, "seg": 8, "wg_per_cu": B.WG_ONE_PER_TILE}],
+                         ids=["persistent-default", "one-per-tile-c512s8"])
+def test_full_384_domain_batch_graph(tuning):
+    """The 384-subdomain configuration, with the default persistent grid and
+    with the launch the autotuner picks on MI355X (one workgroup per tile):
+    graph-captured timestep replayed, sampled domains vs oracle."""
     specs = inputs.batched_specs()
     probs = [inputs.make_domain(s) for s in specs]
     batch = BT.DeviceBatch(probs, B.F64, DEV)
-    plan = batch.plan()
+    plan = batch.plan(tuning)
     say("384 domains", batch.npoints, plan.info())
     g = batch.capture_timestep(plan, seed=11, amplitude=1e-3)
     for _ in range(3):
