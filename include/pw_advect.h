@@ -111,8 +111,9 @@ typedef struct pw_shape {
    chunk      points of the (j, k) plane one workgroup owns in the march
               variant (and in the batched kernel): 256, 512 or 1024.
    seg        x planes one workgroup marches through (>= 1).  In the batched
-              kernel each domain splits its nx planes into ceil(nx / seg)
-              segments of as even a length as possible (at most seg).
+              kernel each domain splits its nx planes into n = ceil(nx / seg)
+              segments of ceil(nx / n) planes (at most seg; the last may be
+              shorter), so a domain's tiles have nearly equal length.
    block      threads per workgroup of the direct variant: 64, 128, 256 or 512.
    wg_per_cu  resident workgroups per compute unit of the persistent batched
               launch (1..8; further capped by LDS), or PW_WG_ONE_PER_TILE:
