@@ -2,7 +2,8 @@
 
 The search itself is ``pw_autotune`` in the HIP library (it times candidate
 launch shapes on the caller's buffers).  This module keys its answers by GPU
-architecture, HIP version, storage type and problem shape, and keeps them in
+architecture, HIP version, the built library, storage type and problem shape,
+and keeps them in
 a JSON file (``$PW_TUNE_CACHE``, else ``~/.cache/pwadvect/tune.json``) so a
 later run reuses them without searching again.
 
@@ -57,6 +58,13 @@ def device_key() -> str:
     return "%s|hip%s" % (arch, torch.version.hip)
 
 
+def library_key() -> str:
+    """Hash of the built HIP library: a rebuilt library (new kernels, a new
+    candidate space) searches again instead of reusing an older choice."""
+    with open(B.LIBRARY, "rb") as f:
+        return "lib" + hashlib.sha256(f.read()).hexdigest()[:12]
+
+
 def shape_key(storage: int, shapes) -> str:
     desc = ";".join("%d,%d,%d,%d,%d" % (s.nx, s.ny, s.nz, s.sy, s.sx) for s in shapes)
     if len(shapes) == 1:
@@ -67,7 +75,7 @@ def shape_key(storage: int, shapes) -> str:
 def tuning_for(batch, reps: int = 5, candidates=None, path: Optional[str] = None, force: bool = False):
     """Cached tuning of a ``batched.DeviceBatch`` (one or many domains); searches on a miss."""
     from . import batched
-    key = device_key() + "|" + shape_key(batch.storage, batch.shapes)
+    key = device_key() + "|" + library_key() + "|" + shape_key(batch.storage, batch.shapes)
     cache = load_cache(path)
     if not force and key in cache and isinstance(cache[key].get("tuning"), dict):
         return cache[key]["tuning"], cache[key].get("ms"), True

@@ -35,3 +35,13 @@ def test_shape_keys_distinguish_storage_and_batches():
 def test_cache_path_env(monkeypatch, tmp_path):
     monkeypatch.setenv("PW_TUNE_CACHE", str(tmp_path / "x.json"))
     assert tune.cache_path() == str(tmp_path / "x.json")
+
+
+def test_library_key_follows_the_built_library(tmp_path, monkeypatch):
+    lib = tmp_path / "libx.so"
+    lib.write_bytes(b"one build")
+    monkeypatch.setattr(B, "LIBRARY", str(lib))
+    k1 = tune.library_key()
+    assert k1 == tune.library_key()
+    lib.write_bytes(b"another build")
+    assert tune.library_key() != k1
