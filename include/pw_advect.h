@@ -33,7 +33,10 @@
  * from the array base: k (vertical) is fastest, a one-point halo surrounds the
  * interior in x and y, there is no vertical halo.  Default strides are
  * sy = nz and sx = (ny + 2) * sy.  All six arrays of one domain share the
- * shape and strides.  Every interior column (i in 1..nx, j in 1..ny) of every
+ * shape and strides.  For HBM throughput, allocate them back to back in
+ * one allocation (each start 256-byte aligned) rather than as six separate
+ * allocations: the latter share the allocator's large alignment, and equal
+ * offsets in the six streams can then fall on the same memory channels.  Every interior column (i in 1..nx, j in 1..ny) of every
  * output is fully written (all k); halo columns of the outputs are never
  * touched.  The caller fills the input halos (including the corner columns,
  * which sv and su read) before the call.

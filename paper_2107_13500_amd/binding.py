@@ -329,18 +329,46 @@ def domain_record(u, v, w, su, sv, sw, tcx, tcy, tzc1, tzc2, tzd1, tzd2,
 # ----------------------------------------------------------------------------
 # convenience: one domain, fields already on the device
 # ----------------------------------------------------------------------------
+def pooled_fields(shape, dtype, device, count: int = 6, align_bytes: int = 256):
+    """`count` arrays of `shape` as views into ONE allocation, back to back
+    (each start rounded up to `align_bytes`).  The recommended HBM layout for
+    a domain's u, v, w, su, sv, sw: separately allocated arrays share the
+    allocator's large alignment, so equal offsets in the six streams can land
+    on the same HBM channels; on MI355X that made the 2048 x 2048 x 64 FP64
+    call 5% slower on some placements, while packed arrays ran at the fast
+    rate on every placement tried."""
+    torch = _torch()
+    n = 1
+    for e in shape:
+        n *= int(e)
+    esize = torch.empty((), dtype=dtype).element_size()
+    step = -(-n * esize // align_bytes) * align_bytes // esize
+    buf = torch.empty(count * step, dtype=dtype, device=device)
+    return [buf[k * step:k * step + n].view(*shape) for k in range(count)]
+
+
 class DeviceDomain:
     """Device copies of one domain's fields and coefficients plus output buffers.
 
     ``u, v, w`` are (nx+2, ny+2, nz) tensors of the storage dtype; the four
     coefficient arrays stay float64 (the ABI keeps them FP64 for every
-    storage type).  Outputs start zeroed so their (never written) halos are 0.
+    storage type).  ``outputs`` (optional) are caller-provided su, sv, sw
+    buffers, e.g. from ``pooled_fields``; otherwise new tensors.  Outputs
+    start zeroed so their (never written) halos are 0.
     """
 
-    def __init__(self, u, v, w, tcx, tcy, tzc1, tzc2, tzd1, tzd2, scales: Optional[PwScales] = None):
+    def __init__(self, u, v, w, tcx, tcy, tzc1, tzc2, tzd1, tzd2, scales: Optional[PwScales] = None,
+                 outputs=None):
         torch = _torch()
         self.u, self.v, self.w = u, v, w
-        self.su, self.sv, self.sw = (torch.zeros_like(u) for _ in range(3))
+        if outputs is None:
+            self.su, self.sv, self.sw = (torch.zeros_like(u) for _ in range(3))
+        else:
+            self.su, self.sv, self.sw = outputs
+            for o in outputs:
+                if o.shape != u.shape or o.dtype != u.dtype or o.device != u.device:
+                    raise ValueError("outputs must match u in shape, dtype and device")
+                o.zero_()
         self.tcx, self.tcy = float(tcx), float(tcy)
         self.tz = [t.to(device=u.device, dtype=torch.float64).contiguous() for t in (tzc1, tzc2, tzd1, tzd2)]
         self.scales = scales
