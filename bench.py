@@ -96,21 +96,30 @@ def settle(fn, stream, seconds=0.3):
 def copy_ceiling(gbytes, steps, warmup, dev, stream, nstreams=1, grids=(16384, 32768, 65536)):
     """Read+write bandwidth of the library's plain streaming copy (pw_probe_copy)
     over `nstreams` buffers of `gbytes` GB each: the best over several grid
-    sizes, since the copy's rate depends on how its concurrent requests fall
-    over the HBM channels (about +-10% between grid sizes)."""
+    sizes and over two layouts (separate allocations, and all buffers packed
+    in one allocation as the stencil's arrays are), since the copy's rate
+    depends on how its concurrent requests fall over the HBM channels."""
     import torch
     from paper_2107_13500_amd import binding as B
     n = int(gbytes * 1e9) // 16 * 16
-    src = [torch.ones(n // 8, dtype=torch.float64, device=dev) for _ in range(nstreams)]
-    dst = [torch.empty_like(a) for a in src]
-    per = {g: time_steps(lambda: B.probe_copy(src, dst, n, g, stream), steps, warmup, stream) for g in grids}
     moved = 2 * n * nstreams
-    del src, dst
-    torch.cuda.empty_cache()
+    per = {}
+    for layout in ("separate", "packed"):
+        if layout == "packed":
+            bufs = B.pooled_fields((n // 8,), torch.float64, dev, count=2 * nstreams)
+        else:
+            bufs = [torch.empty(n // 8, dtype=torch.float64, device=dev) for _ in range(2 * nstreams)]
+        src, dst = bufs[:nstreams], bufs[nstreams:]
+        for a in src:
+            a.fill_(1.0)
+        for g in grids:
+            per[(layout, g)] = time_steps(lambda: B.probe_copy(src, dst, n, g, stream), steps, warmup, stream)
+        del src, dst, bufs
+        torch.cuda.empty_cache()
     best = min(per, key=per.get)
     return {"streams": nstreams, "bytes_per_copy": moved, "ms": round(per[best], 5),
-            "gbs": round(moved / (per[best] * 1e-3) / 1e9, 1), "workgroups": best,
-            "gbs_by_workgroups": {str(g): round(moved / (t * 1e-3) / 1e9, 1) for g, t in per.items()}}
+            "gbs": round(moved / (per[best] * 1e-3) / 1e9, 1), "layout": best[0], "workgroups": best[1],
+            "gbs_by_layout_workgroups": {"%s/%d" % k: round(moved / (t * 1e-3) / 1e9, 1) for k, t in per.items()}}
 
 
 def measured_traffic(kernel_key, chunk, seg):
