@@ -79,3 +79,27 @@ def compare_f64(d: B.DeviceDomain, ref, tol: float = F64_TOL, where: str = ""):
         errs.append(e)
         assert e <= tol, "%s %s: max-norm relative error %.3e > %.1e" % (where, name, e, tol)
     return errs
+
+
+def sampled_columns(nx, ny, n_random=160, seed=11, extra_i=()):
+    """Interior columns (i, j) to check one by one: first and last columns,
+    chunk boundaries (8 columns of 64 levels per 512-point chunk), segment
+    boundaries (128 planes) and `extra_i` planes, plus random columns."""
+    ii = {1, 2, 127, 128, 129, 130, nx // 2, nx - 1, nx} | set(extra_i)
+    jj = {1, 2, 8, 9, 16, 17, ny // 2, ny - 8, ny - 7, ny - 1, ny}
+    cols = {(i, j) for i in ii for j in jj if 1 <= i <= nx and 1 <= j <= ny}
+    rng = np.random.default_rng(seed)
+    cols |= set(zip(rng.integers(1, nx + 1, n_random).tolist(), rng.integers(1, ny + 1, n_random).tolist()))
+    return sorted(cols)
+
+
+def column_oracle(fields, scales, coeffs, cols):
+    """FP64 oracle outputs (ncols, nz) per field at the sampled columns, from
+    each column's 3 x 3-column neighbourhood of the given (stored) fields."""
+    out = [[], [], []]
+    for i, j in cols:
+        nb = [t[i - 1:i + 2, j - 1:j + 2, :].to(torch.float64).cpu().numpy() / s for t, s in zip(fields, scales)]
+        r = oracle.advect(*[np.ascontiguousarray(a) for a in nb], coeffs.tcx, coeffs.tcy, *coeffs.arrays())
+        for f in range(3):
+            out[f].append(r[f][1, 1, :])
+    return [np.stack(o) for o in out]

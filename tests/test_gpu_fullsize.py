@@ -15,7 +15,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_helpers import DEV, F64_TOL, SENTINEL, check_halo_untouched, say
+from gpu_helpers import DEV, F64_TOL, SENTINEL, check_halo_untouched, column_oracle, sampled_columns, say
 from paper_2107_13500_amd import binding as B
 from paper_2107_13500_amd import inputs
 
@@ -28,27 +28,6 @@ UNIT_ROUNDOFF = {B.F32: 2.0 ** -24, B.BF16: 2.0 ** -8, B.F16: 2.0 ** -11}
 def pw2048():
     say("generating pw2048 inputs")
     return inputs.workload("pw2048")
-
-
-def sampled_columns(nx, ny, n_random=160, seed=11):
-    ii = {1, 2, 127, 128, 129, 130, nx // 2, nx - 1, nx}
-    jj = {1, 2, 8, 9, 16, 17, ny // 2, ny - 8, ny - 7, ny - 1, ny}
-    cols = {(i, j) for i in ii for j in jj if 1 <= i <= nx and 1 <= j <= ny}
-    rng = np.random.default_rng(seed)
-    cols |= set(zip(rng.integers(1, nx + 1, n_random).tolist(), rng.integers(1, ny + 1, n_random).tolist()))
-    return sorted(cols)
-
-
-def column_oracle(fields, scales, coeffs, cols):
-    """FP64 oracle outputs (ncols, nz) per field at the sampled columns, from
-    each column's 3 x 3-column neighbourhood of the given (stored) fields."""
-    out = [[], [], []]
-    for i, j in cols:
-        nb = [t[i - 1:i + 2, j - 1:j + 2, :].to(torch.float64).cpu().numpy() / s for t, s in zip(fields, scales)]
-        r = oracle.advect(*[np.ascontiguousarray(a) for a in nb], coeffs.tcx, coeffs.tcy, *coeffs.arrays())
-        for f in range(3):
-            out[f].append(r[f][1, 1, :])
-    return [np.stack(o) for o in out]
 
 
 def device_columns(outputs, scales, cols):

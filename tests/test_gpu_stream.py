@@ -12,7 +12,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_helpers import DEV, F64_TOL, max_rel, same_bits, say
+from gpu_helpers import DEV, F64_TOL, column_oracle, max_rel, positive_zeros, same_bits, sampled_columns, say
 from paper_2107_13500_amd import binding as B
 from paper_2107_13500_amd import inputs
 
@@ -121,3 +121,36 @@ def test_stream_plan_argument_checks():
     st = l.pw_advect_host(sp.handle, None, ins[1].data_ptr(), ins[2].data_ptr(), outs[0].data_ptr(),
                           outs[1].data_ptr(), outs[2].data_ptr(), 0.01, 0.01, *[t.data_ptr() for t in tz], None)
     assert st == -1
+
+
+def test_host_resident_537m_points_sampled_columns():
+    """The paper's largest grid (2048 x 4096 x 64, 537M points) host-resident
+    in pinned memory, overlapped x-slabs of 64 planes as the benchmark runs
+    it: sampled columns (including slab boundaries) against the oracle, k = 1
+    and sw(nz) +0, host output halos untouched."""
+    import gc
+    p = inputs.make_problem(2048, 4096, 64, inputs.SEED_BASE + 5)
+    say("537M points: pinned host arrays")
+    ins, outs, tz = host_arrays(p)
+    sp = B.StreamPlan(B.F64, B.shape_of(ins[0]), chunk=64, nbuffers=3)
+    sp.run(*ins, *outs, p.coeffs.tcx, p.coeffs.tcy, *tz)
+    sp.close()
+    say("537M points: checking sampled columns")
+    cols = sampled_columns(p.nx, p.ny, seed=13, extra_i=(64, 65, 1984, 1985))
+    ref = column_oracle(ins, (1.0, 1.0, 1.0), p.coeffs, cols)
+    I = torch.tensor([c[0] for c in cols])
+    J = torch.tensor([c[1] for c in cols])
+    for name, o, r in zip(("su", "sv", "sw"), outs, ref):
+        g = o[I, J, :].numpy()
+        e = float(np.max(np.abs(g - r)) / np.max(np.abs(r)))
+        say("537M", name, "%d columns, max-norm relative error %.3e" % (len(cols), e))
+        assert e <= F64_TOL
+        assert positive_zeros(g[:, 0])
+        if name == "sw":
+            assert positive_zeros(g[:, -1])
+        for face in (o[0], o[-1], o[:, 0], o[:, -1]):
+            assert bool((face == HOST_SENTINEL).all()), "a host output halo column was written"
+    del ins, outs, p
+    gc.collect()
+    if hasattr(torch._C, "_host_emptyCache"):
+        torch._C._host_emptyCache()   # return the pinned blocks
