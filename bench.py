@@ -318,8 +318,9 @@ def main():
 
     # ---------------- host-resident domains, transfers included ----------------
     if not args.skip_streaming:
-        sizes = [("pw512", inputs.workload("pw512")),
-                 ("pw1024", inputs.make_problem(1024, 1024, 64, inputs.SEED_BASE + 4)), ("pw2048", p)]
+        sizes = [("pw512", p if args.workload == "pw512" else inputs.workload("pw512")),
+                 ("pw1024", inputs.make_problem(1024, 1024, 64, inputs.SEED_BASE + 4)),
+                 ("pw2048", p if args.workload == "pw2048" else inputs.workload("pw2048"))]
         if args.streaming_536m:
             sizes.append(("pw2048x4096", inputs.make_problem(2048, 4096, 64, inputs.SEED_BASE + 5)))
         result["streaming"] = streaming_leg(sizes, log)
