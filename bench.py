@@ -94,32 +94,69 @@ def settle(fn, stream, seconds=0.3):
 
 
 def copy_ceiling(gbytes, steps, warmup, dev, stream, nstreams=1, grids=(16384, 32768, 65536)):
-    """Read+write bandwidth of the library's plain streaming copy (pw_probe_copy)
-    over `nstreams` buffers of `gbytes` GB each: the best over several grid
-    sizes and over two layouts (separate allocations, and all buffers packed
-    in one allocation as the stencil's arrays are), since the copy's rate
-    depends on how its concurrent requests fall over the HBM channels."""
+    """Read+write bandwidth of the library's streaming copy (pw_probe_copy:
+    four words per lane, grid-stride) over `nstreams` buffers of `gbytes` GB
+    each, best over several grid sizes; used with --copy-probe only."""
     import torch
     from paper_2107_13500_amd import binding as B
     n = int(gbytes * 1e9) // 16 * 16
     moved = 2 * n * nstreams
-    per = {}
-    for layout in ("separate", "packed"):
-        if layout == "packed":
-            bufs = B.pooled_fields((n // 8,), torch.float64, dev, count=2 * nstreams)
-        else:
-            bufs = [torch.empty(n // 8, dtype=torch.float64, device=dev) for _ in range(2 * nstreams)]
-        src, dst = bufs[:nstreams], bufs[nstreams:]
-        for a in src:
-            a.fill_(1.0)
-        for g in grids:
-            per[(layout, g)] = time_steps(lambda: B.probe_copy(src, dst, n, g, stream), steps, warmup, stream)
-        del src, dst, bufs
-        torch.cuda.empty_cache()
+    bufs = [torch.empty(n // 8, dtype=torch.float64, device=dev) for _ in range(2 * nstreams)]
+    src, dst = bufs[:nstreams], bufs[nstreams:]
+    for a in src:
+        a.fill_(1.0)
+    per = {g: time_steps(lambda: B.probe_copy(src, dst, n, g, stream), steps, warmup, stream) for g in grids}
     best = min(per, key=per.get)
     return {"streams": nstreams, "bytes_per_copy": moved, "ms": round(per[best], 5),
-            "gbs": round(moved / (per[best] * 1e-3) / 1e9, 1), "layout": best[0], "workgroups": best[1],
-            "gbs_by_layout_workgroups": {"%s/%d" % k: round(moved / (t * 1e-3) / 1e9, 1) for k, t in per.items()}}
+            "gbs": round(moved / (per[best] * 1e-3) / 1e9, 1), "workgroups": best}
+
+
+#: probe family (pw_probe_bandwidth): mode -> (sources, destinations, flag sets tried)
+PROBE_MODES = {
+    "read_only_3": (3, 0, (0, 1)),           # plain / non-temporal loads
+    "write_only_3": (0, 3, (0, 2)),          # non-temporal / cached stores
+    "copy_1x1": (1, 1, (0, 1, 2)),
+    "copy_3x3": (3, 3, (0, 1, 2)),           # the stencil's stream count and read/write ratio
+}
+
+
+def probe_family(gbytes, dev, stream, steps=10, warmup=3):
+    """Attainable HBM bandwidth: read-only, write-only, 1-in/1-out and
+    3-in/3-out streaming over buffers of `gbytes` GB each, the best over the
+    probe's variants (load and store cache policy; one word per lane with one
+    block per workgroup, or four words per lane with one block per workgroup
+    or a 65536-workgroup grid) and two layouts (separate allocations, and all
+    six buffers packed in one allocation as the stencil's arrays are); each
+    variant's rate is the median of three timings."""
+    import torch
+    from paper_2107_13500_amd import binding as B
+    n = int(gbytes * 1e9) // 16 * 16
+    shapes = [(0, 0), (B.PROBE_UNROLL4, 0), (B.PROBE_UNROLL4, 65536)]   # (unroll flag, grid; 0: one per block)
+    best = {m: (0.0, None) for m in PROBE_MODES}
+    sink = torch.empty(n // 256 + 16, dtype=torch.uint8, device=dev)   # 16 B per workgroup of the largest grid
+    for layout in ("separate", "packed"):
+        if layout == "packed":
+            bufs = B.pooled_fields((n // 8,), torch.float64, dev, count=6)
+        else:
+            bufs = [torch.empty(n // 8, dtype=torch.float64, device=dev) for _ in range(6)]
+        for a in bufs[:3]:
+            a.fill_(1.0)
+        for mode, (ni, no, flag_sets) in PROBE_MODES.items():
+            src, dst = bufs[:ni], bufs[3:3 + no]
+            for fl in flag_sets:
+                for unroll, grid in shapes:
+                    # median of three timings, so one short fast sample cannot set the ceiling
+                    ms = sorted(time_steps(lambda: B.probe_bandwidth(src, dst, n, grid, fl | unroll, sink, stream),
+                                           steps, warmup, stream) for _ in range(3))[1]
+                    gbs = (ni + no) * n / (ms * 1e-3) / 1e9
+                    if gbs > best[mode][0]:
+                        best[mode] = (gbs, {"layout": layout, "flags": fl | unroll,
+                                            "words_per_lane": 4 if unroll else 1,
+                                            "workgroups": grid or "one per block"})
+        del bufs, src, dst
+        torch.cuda.empty_cache()
+    del sink
+    return {m: {"gbs": round(g, 1), "config": c} for m, (g, c) in best.items()}
 
 
 def measured_traffic(kernel_key, chunk, seg):
@@ -273,12 +310,20 @@ def main():
         t = measured_traffic("pw_march_f64_%s" % args.workload, info["chunk"], info["seg"])
         result["roofline"]["traffic"] = None if t is None else int(round(t))
 
-    ceiling = copy_ceiling(2.0, 10, 3, dev, stream, nstreams=1)
-    ceiling3 = copy_ceiling(2.15, 10, 3, dev, stream, nstreams=3)
-    result["roofline"]["copy_ceiling_gbs"] = ceiling["gbs"]
-    result["roofline"]["copy_ceiling_3x3_streams_gbs"] = ceiling3["gbs"]
-    result["roofline"]["frac_of_copy_ceiling"] = round(achieved / max(ceiling["gbs"], ceiling3["gbs"]), 4)
-    log("copy ceilings", ceiling, ceiling3)
+    # attainable bandwidth on this card: buffers of one FP64 array of the
+    # headline grid each (2.15 GB), read only, write only and mixed
+    probes = probe_family(2.15, dev, stream)
+    result["roofline"]["probes"] = probes
+    mixed = max(probes["copy_1x1"]["gbs"], probes["copy_3x3"]["gbs"])
+    result["roofline"]["frac_of_copy_3x3"] = round(achieved / probes["copy_3x3"]["gbs"], 4)
+    result["roofline"]["frac_of_best_mixed_copy"] = round(achieved / mixed, 4)
+    log("probe family", probes)
+
+    # ---------------- the paper's Table I size (512 x 512 x 64), FP64 ----------------
+    small = None
+    if args.workload != "pw512":
+        small = small_workload_leg("pw512", tuning, dev, stream, args.steps, args.warmup, log)
+        result["pw512"] = small["record"]
 
     # ---------------- storage-precision variants (outputs kept for the error check) ----------------
     kept = {}
@@ -336,6 +381,13 @@ def main():
         torch.cuda.synchronize()
         result["parity_f64"] = errors_vs(ref, d64.outputs, (1.0, 1.0, 1.0), nx, ny)
         log("FP64 parity", result["parity_f64"]["max_rel"])
+        if small is not None:
+            import oracle
+            sref = oracle.advect_problem(small["problem"], threads=threads)
+            result["pw512"]["parity_f64"] = errors_vs(sref, small["domain"].outputs, (1.0, 1.0, 1.0),
+                                                      small["problem"].nx, small["problem"].ny)
+            log("pw512 FP64 parity", result["pw512"]["parity_f64"]["max_rel"])
+            del sref
         for name, (outs, outs_s) in kept.items():
             result["precision"][name]["error_vs_f64_oracle"] = errors_vs(ref, outs, outs_s, nx, ny)
             log(name, "error", result["precision"][name]["error_vs_f64_oracle"]["max_rel"])
@@ -344,15 +396,99 @@ def main():
             result["batched"][name]["max_rel_err_sampled"] = batched_errors(batch, threads)
             log("batched", name, "error", result["batched"][name]["max_rel_err_sampled"])
 
+    failures = parity_gate(result)
+    if failures:
+        result["value"] = None
+        result["parity_failures"] = failures
+        log("parity gate FAILED:", failures)
     print(json.dumps(result), flush=True)
+    if failures:
+        sys.exit(4)
+
+
+def parity_gate(result):
+    """Every error figure of a benchmark record against its acceptance bound
+    (the bounds the GPU tests use); returns the violations, empty if none.
+    A figure that was not computed (e.g. --skip-cpu) is not checked."""
+    from paper_2107_13500_amd import metrics
+    fails = []
+
+    def check(where, err, bound):
+        if err is None:
+            return
+        if not (err <= bound):   # NaN fails too
+            fails.append("%s: max-norm relative error %r > %g" % (where, err, bound))
+
+    check("f64", (result.get("parity_f64") or {}).get("max_rel"), metrics.F64_PARITY_TOL)
+    check("pw512 f64", ((result.get("pw512") or {}).get("parity_f64") or {}).get("max_rel"),
+          metrics.F64_PARITY_TOL)
+    for name, rec in (result.get("precision") or {}).items():
+        check("storage %s" % name, (rec.get("error_vs_f64_oracle") or {}).get("max_rel"),
+              metrics.STORAGE_ERROR_BOUND[name])
+    for name, rec in (result.get("batched") or {}).items():
+        check("batched %s" % name, rec.get("max_rel_err_sampled"), metrics.BATCHED_ERROR_BOUND[name])
+    return fails
+
+
+def small_workload_leg(name, tuning, dev, stream, steps, warmup, log):
+    """One more FP64 workload (inputs resident in HBM, six arrays packed in one
+    allocation), timed like the headline with its own roofline; its outputs are
+    kept for the parity check against the oracle."""
+    import torch
+    from paper_2107_13500_amd import binding as B
+    from paper_2107_13500_amd import inputs, metrics
+    p = inputs.workload(name)
+    c = p.coeffs
+    tz = [torch.from_numpy(a).to(dev) for a in c.arrays()]
+    pool = B.pooled_fields(p.u.shape, torch.float64, dev)
+    for k, a in enumerate((p.u, p.v, p.w)):
+        pool[k].copy_(torch.from_numpy(a))
+    d = B.DeviceDomain(*pool[:3], c.tcx, c.tcy, *tz, outputs=pool[3:])
+    plan = B.Plan(B.F64, [B.shape_of(pool[0])], tuning)
+    info = plan.info()
+    settle(lambda: d.run(plan, stream), stream)
+    ms = time_steps(lambda: d.run(plan, stream), max(steps, 50), warmup, stream)
+    abytes = metrics.algorithmic_bytes(p.nx, p.ny, p.nz, 8)
+    achieved = abytes / (ms * 1e-3) / 1e9
+    rec = {"workload": "%s: one %dx%dx%d FP64 domain (the paper's Table I size), su+sv+sw per call"
+                       % (name, p.nx, p.ny, p.nz),
+           "points": p.npoints, "ms_per_call": round(ms, 5),
+           "gpoints_per_s": round(p.npoints / (ms * 1e-3) / 1e9, 3),
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                        "algorithmic_bytes_per_launch": abytes},
+           "per_launch_ms": per_launch(lambda: d.run(plan, stream), 20, stream),
+           "chunk": info["chunk"], "seg": info["seg"], "workgroups": info["workgroups"],
+           "note": "0.81 GB of arrays against the 256 MB last-level cache: repeated calls may hit it"}
+    if info["variant"] == B.VARIANT_MARCH:
+        t = measured_traffic("pw_march_f64_%s" % name, info["chunk"], info["seg"])
+        rec["roofline"]["traffic"] = None if t is None else int(round(t))
+    log(name, rec)
+    return {"record": rec, "problem": p, "domain": d, "plan": plan}
 
 
 def read_power_w():
-    """Current socket power of GPU 0 in W from amd-smi, or None."""
+    """Current socket power of GPU 0 in W from amd-smi, or None.  amd-smi runs
+    in a process group of its own, which is killed once the reading is in (or
+    after 20 s), so no helper process it started outlives the reading."""
+    import signal
     import subprocess
     try:
-        out = subprocess.run(["amd-smi", "metric", "-g", "0", "-p", "--json"], capture_output=True, text=True,
-                             timeout=20).stdout
+        proc = subprocess.Popen(["amd-smi", "metric", "-g", "0", "-p", "--json"], stdout=subprocess.PIPE,
+                                stderr=subprocess.DEVNULL, text=True, start_new_session=True)
+    except OSError:
+        return None
+    try:
+        out, _ = proc.communicate(timeout=20)
+    except subprocess.TimeoutExpired:
+        out = ""
+    finally:
+        try:
+            os.killpg(proc.pid, signal.SIGKILL)
+        except (ProcessLookupError, PermissionError):
+            pass
+        proc.wait()
+    try:
         data = json.loads(out)
         rec = data["gpu_data"][0] if isinstance(data, dict) else data[0]
         return float(rec["power"]["socket_power"]["value"])

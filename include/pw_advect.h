@@ -331,6 +331,30 @@ int32_t pw_autotune_candidates(int32_t batched, pw_tuning *out, int32_t capacity
 int32_t pw_probe_copy(const void *const *src, void *const *dst, int32_t nstreams,
                       int64_t bytes, int32_t workgroups, void *stream);
 
+/* Measurement utility (no part of the stencil): the general form of
+   pw_probe_copy.  Reads nsrc (0..3) and writes ndst (0..3) buffers of
+   `bytes` bytes each (a multiple of 16), not both zero:
+     nsrc > 0, ndst > 0  dst[s] = src[s mod nsrc] (a copy);
+     nsrc = 0            dst[s] receives a fixed pattern (write only);
+     ndst = 0            the sources are read and XOR-reduced (read only);
+                         `sink` (device, 16 bytes per workgroup) receives a
+                         word only if the reduction hits a fixed marker, so
+                         the loads cannot be dropped by the compiler.
+   flags: PW_PROBE_* bits -- non-temporal loads (default plain), cached
+   stores (default non-temporal), four 16-byte words per lane and buffer in
+   each block (default one).  The main loop is free of per-lane conditions;
+   the ragged tail is handled separately.  src, dst: host arrays of device
+   pointers (16-byte aligned); sink may be NULL when ndst > 0.  workgroups:
+   grid size, 0 = one workgroup per block (256 lanes x 1 or 4 words per
+   buffer); a smaller grid walks the blocks grid-stride.  Asynchronous on
+   `stream`.  Returns PW_ERR_INVALID_ARG for bad counts, sizes or flags,
+   PW_ERR_ALIGNMENT for a misaligned pointer. */
+#define PW_PROBE_NT_LOADS 1
+#define PW_PROBE_CACHED_STORES 2
+#define PW_PROBE_UNROLL4 4
+int32_t pw_probe_bandwidth(const void *const *src, int32_t nsrc, void *const *dst, int32_t ndst,
+                           int64_t bytes, int32_t workgroups, int32_t flags, void *sink, void *stream);
+
 /* Human-readable name of a status code (static string). */
 const char *pw_status_string(int32_t status);
 

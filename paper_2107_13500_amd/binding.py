@@ -78,6 +78,8 @@ SIGNATURES = {
     "pw_advect_host": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(PwScales)]),
     "pw_probe_copy": (c_int32, [POINTER(c_void_p), POINTER(c_void_p), c_int32, c_int64, c_int32, c_void_p]),
+    "pw_probe_bandwidth": (c_int32, [POINTER(c_void_p), c_int32, POINTER(c_void_p), c_int32, c_int64, c_int32,
+                                     c_int32, c_void_p, c_void_p]),
     "pw_status_string": (ctypes.c_char_p, [c_int32]),
     "pw_last_hip_error": (c_int32, []),
 }
@@ -238,9 +240,41 @@ class Plan:
         self.close()
 
 
+def _normalised(s: PwShape):
+    sy = s.sy or s.nz
+    return (s.nx, s.ny, s.nz, sy, s.sx or (s.ny + 2) * sy)
+
+
+def check_fields(storage: int, shape: PwShape, fields, tz) -> None:
+    """Raise ValueError unless the six field tensors are CUDA tensors of the
+    storage dtype, on one device, each spanning `shape` (extents and strides),
+    and the four coefficient tensors are contiguous CUDA float64 tensors of at
+    least nz values on the same device.  Run before any pointer reaches the
+    library, whose kernels trust these extents."""
+    torch = _torch()
+    want = _normalised(shape)
+    dt = torch_dtype(storage)
+    dev = fields[0].device if len(fields) else None
+    for name, t in zip(("u", "v", "w", "su", "sv", "sw"), fields):
+        if t.dtype != dt:
+            raise ValueError("%s has dtype %s; the plan stores %s" % (name, t.dtype, dt))
+        if _normalised(shape_of(t)) != want:
+            raise ValueError("%s has shape %s and strides %s; the plan expects (nx, ny, nz, sy, sx) = %s"
+                             % (name, tuple(t.shape), t.stride(), want))
+    for name, t in zip(("tzc1", "tzc2", "tzd1", "tzd2"), tz):
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() < shape.nz:
+            raise ValueError("%s must be a contiguous float64 tensor of at least nz = %d values" % (name, shape.nz))
+    for name, t in zip(("u", "v", "w", "su", "sv", "sw", "tzc1", "tzc2", "tzd1", "tzd2"), (*fields, *tz)):
+        if not t.is_cuda or t.device != dev:
+            raise ValueError("%s must be a CUDA tensor on %s" % (name, dev))
+
+
 def advect(plan: Plan, u, v, w, su, sv, sw, tcx: float, tcy: float, tzc1, tzc2, tzd1, tzd2,
            scales: Optional[PwScales] = None, stream=None) -> None:
     """pw_advect on torch device tensors (asynchronous on `stream`)."""
+    if plan.ndomains != 1:
+        raise ValueError("pw_advect needs a single-domain plan")
+    check_fields(plan.storage, plan.shapes[0], (u, v, w, su, sv, sw), (tzc1, tzc2, tzd1, tzd2))
     st = lib().pw_advect(plan.handle, u.data_ptr(), v.data_ptr(), w.data_ptr(),
                          su.data_ptr(), sv.data_ptr(), sw.data_ptr(), float(tcx), float(tcy),
                          tzc1.data_ptr(), tzc2.data_ptr(), tzd1.data_ptr(), tzd2.data_ptr(),
@@ -271,6 +305,20 @@ def probe_copy(srcs, dsts, nbytes: int, workgroups: int = 0, stream=None) -> Non
     sp = (c_void_p * n)(*[t.data_ptr() for t in srcs])
     dp = (c_void_p * n)(*[t.data_ptr() for t in dsts])
     check(lib().pw_probe_copy(sp, dp, n, int(nbytes), int(workgroups), stream_handle(stream)), "pw_probe_copy")
+
+
+PROBE_NT_LOADS, PROBE_CACHED_STORES, PROBE_UNROLL4 = 1, 2, 4
+
+
+def probe_bandwidth(srcs, dsts, nbytes: int, workgroups: int = 0, flags: int = 0, sink=None, stream=None) -> None:
+    """pw_probe_bandwidth: read ``srcs`` and write ``dsts`` (lists of device
+    tensors, either may be empty); ``sink`` is a device tensor of at least 16
+    bytes per workgroup, needed when ``dsts`` is empty."""
+    sp = (c_void_p * max(1, len(srcs)))(*[t.data_ptr() for t in srcs])
+    dp = (c_void_p * max(1, len(dsts)))(*[t.data_ptr() for t in dsts])
+    check(lib().pw_probe_bandwidth(sp, len(srcs), dp, len(dsts), int(nbytes), int(workgroups), int(flags),
+                                   sink.data_ptr() if sink is not None else None, stream_handle(stream)),
+          "pw_probe_bandwidth")
 
 
 class StreamPlan:
@@ -316,8 +364,10 @@ def domain_args_tensor(records: Sequence[PwDomainArgs], device):
 
 def domain_record(u, v, w, su, sv, sw, tcx, tcy, tzc1, tzc2, tzd1, tzd2,
                   scales: Optional[PwScales] = None) -> PwDomainArgs:
+    """pw_domain_args of one domain's device tensors (checked like ``advect``'s)."""
     r = PwDomainArgs()
     r.shape = shape_of(u)
+    check_fields(storage_of(u.dtype), r.shape, (u, v, w, su, sv, sw), (tzc1, tzc2, tzd1, tzd2))
     r.u, r.v, r.w = u.data_ptr(), v.data_ptr(), w.data_ptr()
     r.su, r.sv, r.sw = su.data_ptr(), sv.data_ptr(), sw.data_ptr()
     r.tcx, r.tcy = float(tcx), float(tcy)

@@ -76,14 +76,17 @@ bool march_possible(const pw_shape& s) {
     return s.sy == s.nz && s.nz <= kMarchMaxNz && s.nx <= (1 << 30);
 }
 
-int32_t auto_seg(const pw_shape& s, int32_t nchunks) {
-    // enough workgroups to fill 256 CUs many times over (about 16 per CU),
-    // segments long enough that re-reading the two boundary planes stays a
-    // few percent, and all segments of nearly equal length (measured on
-    // 2048 x 2048 x 64 with two planes in flight: 128 planes beat 64 by 1%
-    // for FP64 and FP32 and tie for the 16-bit types; an uneven split such
-    // as 192 costs 7%)
-    const int64_t target = 4096;
+int32_t auto_seg(int32_t storage, const pw_shape& s, int32_t nchunks) {
+    // Many tiles (the boundary planes each tile re-reads stay a few percent
+    // of its traffic only with segments of 16 planes or more), all segments
+    // of nearly equal length.  Measured with the compact tile order on
+    // 512 x 512 x 64 and 2048 x 2048 x 64 over chunks 512/1024 and segments
+    // of 16..256 planes for every storage type: 16 planes are best on the
+    // small grid for all types; on the large grid FP64 and the 16-bit types
+    // are best at about 8192 tiles (64 planes) and the 4-byte types at about
+    // 2048 (256 planes), 0.5-1% ahead of 128 planes; an uneven split (such as
+    // 192 planes over 2048) costs 7%.
+    const int64_t target = elem_bytes(storage) == 4 ? 2048 : 8192;
     int64_t seg = (int64_t)s.nx * nchunks / target;
     seg = std::max<int64_t>(seg, 16);
     seg = std::min<int64_t>(seg, 256);
@@ -107,12 +110,15 @@ int32_t resolve_launch(int32_t storage, const pw_shape& s, const pw_tuning& t, L
         r.chunk = chunk;
         r.block = 256;
         r.nchunks = (int32_t)(((int64_t)s.ny * s.nz + chunk - 1) / chunk);
-        r.seg = t.seg ? std::min(t.seg, s.nx) : auto_seg(s, r.nchunks);
+        r.seg = t.seg ? std::min(t.seg, s.nx) : auto_seg(storage, s, r.nchunks);
         r.nseg = (s.nx + r.seg - 1) / r.seg;
         r.wpad = ((chunk + 2 * s.nz) + 3) / 4 * 4;
         r.lds_bytes = march_lds_bytes(storage, r.wpad);
         if (r.lds_bytes > kMaxDynamicLds) return PW_ERR_UNSUPPORTED;
-        r.workgroups = (int64_t)r.nchunks * r.nseg;
+        r.tiles = (int64_t)r.nchunks * r.nseg;
+        // compact tile order (pw_march_kernel) when every XCD owns a chunk
+        r.cpx = r.nchunks >= kNumXcd ? (r.nchunks + kNumXcd - 1) / kNumXcd : 0;
+        r.workgroups = r.cpx > 0 ? (int64_t)kNumXcd * r.cpx * r.nseg : r.tiles;
         if (r.workgroups >= (int64_t(1) << 31)) return PW_ERR_INVALID_ARG;
     } else {
         const int32_t block = t.block ? t.block : 256;
@@ -125,8 +131,8 @@ int32_t resolve_launch(int32_t storage, const pw_shape& s, const pw_tuning& t, L
         r.nseg = s.nx;
         r.workgroups = (int64_t)r.nchunks * s.nx;
         r.lds_bytes = 0;
+        r.tiles = r.workgroups;
     }
-    r.tiles = r.workgroups;
     *L = r;
     return PW_OK;
 }
@@ -144,7 +150,7 @@ hipError_t launch_march(const DomainArgs& d, const Launch& L, hipStream_t stream
                                        hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynamicLds);
     });
     if (attr_err != hipSuccess) return attr_err;
-    MarchGeom g{L.nchunks, L.nseg, L.seg, L.wpad};
+    MarchGeom g{L.nchunks, L.nseg, L.seg, L.wpad, L.cpx};
     hipLaunchKernelGGL(kern, dim3((unsigned)L.workgroups), dim3(256), (size_t)L.lds_bytes, stream, d, g);
     return hipGetLastError();
 }

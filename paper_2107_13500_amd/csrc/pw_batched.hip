@@ -38,6 +38,25 @@ __device__ __forceinline__ bool shape_matches(const pw_shape& a, const BatchDoma
 
 __device__ __forceinline__ float scale_or_one(float s) { return s > 0.0f ? s : 1.0f; }
 
+// A record's scale must be 0 (meaning 1) or a finite positive power of two
+// (normal or subnormal), as pw_advect requires of its scales; folding such
+// scales into the coefficients is exact.
+__device__ __forceinline__ bool scale_ok(float s) {
+    const uint32_t b = __float_as_uint(s);
+    if (b == 0u) return true;                       // +0: default scale
+    if (b >> 31) return false;                      // negative or -0
+    const uint32_t e = (b >> 23) & 0xffu, m = b & 0x7fffffu;
+    if (e == 0xffu) return false;                   // Inf or NaN
+    return e != 0u ? m == 0u : __popc(m) == 1;
+}
+
+__device__ __forceinline__ bool scales_ok(const pw_scales& sc) {
+    bool ok = true;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) ok = ok && scale_ok(sc.in_scale[f]) && scale_ok(sc.out_scale[f]);
+    return ok;
+}
+
 template <typename ST>
 __device__ __forceinline__ DomainArgs domain_from(const pw_domain_args& a, const BatchDomain& b) {
     DomainArgs d{};
@@ -122,7 +141,8 @@ __global__ __launch_bounds__(NT) void pw_batched_kernel(const BatchDomain* __res
         const int c = (int)(local % b.nchunks);
         const int s = (int)(local / b.nchunks);
         const pw_domain_args& a = args[dom];
-        if (!shape_matches(a.shape, b) || !a.u || !a.v || !a.w || !a.su || !a.sv || !a.sw) {
+        if (!shape_matches(a.shape, b) || !a.u || !a.v || !a.w || !a.su || !a.sv || !a.sw ||
+            (scaled_type<ST>::value && !scales_ok(a.scales))) {
             if (threadIdx.x == 0 && local == 0) atomicAdd(errors, 1ull);
             continue;   // uniform over the workgroup
         }
@@ -193,7 +213,7 @@ __global__ __launch_bounds__(256) void pw_halo_kernel(const BatchDomain* __restr
 }
 
 // SplitMix64 finaliser (Steele, Lea and Flood, OOPSLA 2014).
-__device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
+__host__ __device__ __forceinline__ uint64_t splitmix64(uint64_t x) {
     x += 0x9e3779b97f4a7c15ull;
     x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
     x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
@@ -251,9 +271,19 @@ __global__ __launch_bounds__(256) void pw_perturb_kernel(const BatchDomain* __re
 
 __global__ void pw_bump_kernel(unsigned long long* call) { *call += 1ull; }
 
+// Everything one launch of the batched kernel needs besides the records.
+struct BatchedLaunch {
+    const BatchDomain* table;
+    int32_t ndomains;
+    int64_t tiles;
+    int64_t workgroups;
+    int64_t lds_bytes;
+    unsigned long long* errors;
+    bool vec_shapes;
+};
+
 template <typename ST, int P, int KIND>
-hipError_t launch_batched(const pw_plan* p, const pw_domain_args* args, hipStream_t stream) {
-    const BatchState& B = p->batch;
+hipError_t launch_batched(const BatchedLaunch& bl, const pw_domain_args* args, hipStream_t stream) {
     auto kern = pw_batched_kernel<ST, 256, P, KIND>;
     static std::once_flag once;
     static hipError_t attr_err = hipSuccess;
@@ -262,9 +292,8 @@ hipError_t launch_batched(const pw_plan* p, const pw_domain_args* args, hipStrea
                                        hipFuncAttributeMaxDynamicSharedMemorySize, kMaxDynamicLds);
     });
     if (attr_err != hipSuccess) return attr_err;
-    hipLaunchKernelGGL(kern, dim3((unsigned)B.launch.workgroups), dim3(256), (size_t)B.launch.lds_bytes, stream,
-                       B.d_table, p->ndomains, B.launch.tiles, args, B.d_errors,
-                       B.vec_shapes ? 1 : 0);
+    hipLaunchKernelGGL(kern, dim3((unsigned)bl.workgroups), dim3(256), (size_t)bl.lds_bytes, stream, bl.table,
+                       bl.ndomains, bl.tiles, args, bl.errors, bl.vec_shapes ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -312,21 +341,35 @@ int batched_occupancy(int32_t storage, int32_t chunk, int32_t kind, int64_t lds_
 }
 
 template <typename ST, int P>
-hipError_t dispatch_kind(const pw_plan* p, const pw_domain_args* args, hipStream_t stream) {
-    switch (p->batch.kind) {
-        case kFixedNz: return launch_batched<ST, P, kFixedNz>(p, args, stream);
-        case kVector: return launch_batched<ST, P, kVector>(p, args, stream);
-        case kAny: return launch_batched<ST, P, kAny>(p, args, stream);
+hipError_t dispatch_kind(int32_t kind, const BatchedLaunch& bl, const pw_domain_args* args, hipStream_t stream) {
+    switch (kind) {
+        case kFixedNz: return launch_batched<ST, P, kFixedNz>(bl, args, stream);
+        case kVector: return launch_batched<ST, P, kVector>(bl, args, stream);
+        case kAny: return launch_batched<ST, P, kAny>(bl, args, stream);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename ST>
-hipError_t dispatch_batched(const pw_plan* p, const pw_domain_args* args, hipStream_t stream) {
-    switch (p->batch.launch.chunk) {
-        case 256: return dispatch_kind<ST, 256>(p, args, stream);
-        case 512: return dispatch_kind<ST, 512>(p, args, stream);
-        case 1024: return dispatch_kind<ST, 1024>(p, args, stream);
+hipError_t dispatch_chunk(int32_t chunk, int32_t kind, const BatchedLaunch& bl, const pw_domain_args* args,
+                          hipStream_t stream) {
+    switch (chunk) {
+        case 256: return dispatch_kind<ST, 256>(kind, bl, args, stream);
+        case 512: return dispatch_kind<ST, 512>(kind, bl, args, stream);
+        case 1024: return dispatch_kind<ST, 1024>(kind, bl, args, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t dispatch_batched(int32_t storage, int32_t chunk, int32_t kind, const BatchedLaunch& bl,
+                            const pw_domain_args* args, hipStream_t stream) {
+    switch (storage) {
+        case PW_F64: return dispatch_chunk<double>(chunk, kind, bl, args, stream);
+        case PW_F32: return dispatch_chunk<float>(chunk, kind, bl, args, stream);
+        case PW_BF16: return dispatch_chunk<bf16_t>(chunk, kind, bl, args, stream);
+        case PW_F16: return dispatch_chunk<f16_t>(chunk, kind, bl, args, stream);
+        case PW_I16: return dispatch_chunk<fx16_t>(chunk, kind, bl, args, stream);
+        case PW_I32: return dispatch_chunk<fx32_t>(chunk, kind, bl, args, stream);
         default: return hipErrorInvalidValue;
     }
 }
@@ -345,72 +388,71 @@ int64_t max_points(const pw_plan* p) {
 
 }  // namespace
 
-int32_t batched_plan_init(pw_plan* p) {
-    BatchState& B = p->batch;
-    for (const pw_shape& s : p->shapes) {
-        if (!march_possible(s)) return PW_OK;   // batched entry points will report PW_ERR_UNSUPPORTED
-        if ((int64_t)s.nx * s.ny * s.nz >= (int64_t(1) << 31)) return PW_OK;
-    }
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(nullptr, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return PW_ERR_CAPTURE;
+// Tile split of one domain: nchunks chunks of `chunk` points per plane, x
+// range split into nseg segments of even length (at most seg_max planes:
+// nseg = ceil(nx / seg_max) parts of ceil(nx / nseg) planes, which start at or
+// before plane nx and cover every plane).
+__host__ __device__ inline void domain_tiles(int32_t nx, int32_t ny, int32_t nz, int32_t chunk, int32_t seg_max,
+                                             BatchDomain* b) {
+    b->nx = nx;
+    b->ny = ny;
+    b->nz = nz;
+    b->nchunks = (int32_t)(((int64_t)ny * nz + chunk - 1) / chunk);
+    b->nseg = (nx + seg_max - 1) / seg_max;
+    b->seg = (nx + b->nseg - 1) / b->nseg;
+}
 
-    const pw_tuning& t = p->tuning;
+// Launch shape of the batched kernel for a list of (normalised) shapes:
+// chunk, segment bound, LDS, code-path kind, total tiles and grid.  Allocates
+// nothing.  Returns PW_OK with L->tiles == 0 if a shape cannot use the
+// batched kernel (march variant impossible, or 2^31 points or more).
+int32_t batched_launch_shape(int32_t storage, const pw_shape* shapes, int32_t n, const pw_tuning& t, Launch* L,
+                             int32_t* kind, bool* vec_out) {
+    *L = Launch{};
+    for (int32_t d = 0; d < n; ++d) {
+        pw_shape s;
+        const int32_t rc = normalize_shape(shapes[d], &s);
+        if (rc != PW_OK) return rc;
+        if (!march_possible(s) || (int64_t)s.nx * s.ny * s.nz >= (int64_t(1) << 31)) return PW_OK;
+    }
     const int32_t chunk = t.chunk ? t.chunk : 512;
     if (chunk != 256 && chunk != 512 && chunk != 1024) return PW_ERR_INVALID_ARG;
     if (t.seg < 0 || t.wg_per_cu < PW_WG_ONE_PER_TILE || t.wg_per_cu > 8) return PW_ERR_INVALID_ARG;
+    const int32_t seg_max = t.seg ? t.seg : 64;
+    const int64_t vw = 16 / elem_bytes(storage);
     int32_t nzmax = 0;
-    for (const pw_shape& s : p->shapes) nzmax = std::max(nzmax, s.nz);
-
-    std::vector<BatchDomain> table(p->ndomains);
     int64_t tiles = 0;
-    bool vec = true;
-    const int64_t vw = 16 / elem_bytes(p->storage);
-    int32_t seg_used = 0;
-    for (int32_t d = 0; d < p->ndomains; ++d) {
-        const pw_shape& s = p->shapes[d];
-        BatchDomain& b = table[d];
-        b.nx = s.nx;
-        b.ny = s.ny;
-        b.nz = s.nz;
-        b.sy = s.sy;
-        b.sx = s.sx;
-        b.nchunks = (int32_t)(((int64_t)s.ny * s.nz + chunk - 1) / chunk);
-        // segment length: at most the tuned (else 64) planes, as even as
-        // possible -- nseg = ceil(nx / seg) parts of ceil(nx / nseg) planes,
-        // which start at or before plane nx and cover every plane
-        const int32_t seg = t.seg ? t.seg : 64;
-        seg_used = seg;
-        b.nseg = (s.nx + seg - 1) / seg;
-        b.seg = (s.nx + b.nseg - 1) / b.nseg;
-        b.tile_begin = tiles;
+    bool vec = true, fixed_nz = true;
+    for (int32_t d = 0; d < n; ++d) {
+        pw_shape s;
+        (void)normalize_shape(shapes[d], &s);   // checked above
+        BatchDomain b{};
+        domain_tiles(s.nx, s.ny, s.nz, chunk, seg_max, &b);
         tiles += (int64_t)b.nchunks * b.nseg;
+        nzmax = std::max(nzmax, s.nz);
         if (s.nz % vw || s.sx % vw || s.sy % vw) vec = false;
+        fixed_nz = fixed_nz && (s.nz == 64 || s.nz == 96 || s.nz == 128);
     }
-    Launch L{};
-    L.variant = PW_VARIANT_MARCH;
-    L.chunk = chunk;
-    L.seg = seg_used;
-    L.block = 256;
-    L.wpad = ((chunk + 2 * nzmax) + 3) / 4 * 4;
-    L.lds_bytes = march_lds_bytes(p->storage, L.wpad);
-    if (L.lds_bytes > kMaxDynamicLds) return PW_ERR_UNSUPPORTED;
-    L.tiles = tiles;
-
-    int dev = 0;
+    Launch r{};
+    r.variant = PW_VARIANT_MARCH;
+    r.chunk = chunk;
+    r.seg = seg_max;
+    r.block = 256;
+    r.wpad = ((chunk + 2 * nzmax) + 3) / 4 * 4;
+    r.lds_bytes = march_lds_bytes(storage, r.wpad);
+    if (r.lds_bytes > kMaxDynamicLds) return PW_ERR_UNSUPPORTED;
+    r.tiles = tiles;
+    int dev = 0, cus = 0;
     hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return report_hip(e);
-    hipDeviceProp_t prop;
-    e = hipGetDeviceProperties(&prop, dev);
-    if (e != hipSuccess) return report_hip(e);
-    const int64_t by_lds = std::max<int64_t>(1, kLdsPerCu / std::max<int64_t>(L.lds_bytes, 1));
+    const int32_t k = !vec ? kAny : (fixed_nz ? kFixedNz : kVector);
+    const int64_t by_lds = std::max<int64_t>(1, kLdsPerCu / std::max<int64_t>(r.lds_bytes, 1));
     int64_t per_cu = std::min<int64_t>(by_lds, 8);
-    bool fixed_nz = true;
-    for (const pw_shape& s : p->shapes) fixed_nz = fixed_nz && (s.nz == 64 || s.nz == 96 || s.nz == 128);
-    B.kind = !vec ? kAny : (fixed_nz ? kFixedNz : kVector);
-    const int occ = batched_occupancy(p->storage, chunk, B.kind, L.lds_bytes);
+    const int occ = batched_occupancy(storage, chunk, k, r.lds_bytes);
     if (occ > 0) per_cu = std::min<int64_t>(per_cu, occ);
     if (t.wg_per_cu > 0) per_cu = std::min<int64_t>(per_cu, t.wg_per_cu);
-    L.workgroups = std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)prop.multiProcessorCount * per_cu));
+    r.workgroups = std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)cus * per_cu));
     // One workgroup per tile: the kernel's tile loop then runs once per
     // workgroup, and the hardware dispatches tiles in order as workgroups
     // retire, so the workgroups on neighbouring chunks stay in step (their
@@ -419,11 +461,39 @@ int32_t batched_plan_init(pw_plan* p) {
     // faster than the best persistent grid for FP64, FP32 and BF16.
     if (t.wg_per_cu == PW_WG_ONE_PER_TILE) {
         if (tiles >= (int64_t(1) << 31)) return PW_ERR_UNSUPPORTED;
-        L.workgroups = tiles;
+        r.workgroups = tiles;
     }
-    L.nchunks = 0;
-    L.nseg = 0;
+    *L = r;
+    *kind = k;
+    *vec_out = vec;
+    return PW_OK;
+}
 
+int32_t batched_plan_init(pw_plan* p) {
+    BatchState& B = p->batch;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(nullptr, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return PW_ERR_CAPTURE;
+    Launch L{};
+    int32_t kind = kAny;
+    bool vec = false;
+    int32_t rc = batched_launch_shape(p->storage, p->shapes.data(), p->ndomains, p->tuning, &L, &kind, &vec);
+    if (rc != PW_OK) return rc;
+    if (L.tiles == 0) return PW_OK;   // batched entry points will report PW_ERR_UNSUPPORTED
+
+    std::vector<BatchDomain> table(p->ndomains);
+    int64_t tiles = 0;
+    for (int32_t d = 0; d < p->ndomains; ++d) {
+        const pw_shape& s = p->shapes[d];
+        BatchDomain& b = table[d];
+        domain_tiles(s.nx, s.ny, s.nz, L.chunk, L.seg, &b);
+        b.sy = s.sy;
+        b.sx = s.sx;
+        b.tile_begin = tiles;
+        tiles += (int64_t)b.nchunks * b.nseg;
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return report_hip(e);
     void* mem = nullptr;
     const size_t tbytes = sizeof(BatchDomain) * table.size();
     // one allocation: the tile table, then the error count
@@ -445,6 +515,7 @@ int32_t batched_plan_init(pw_plan* p) {
     B.launch = L;
     B.device = dev;
     B.vec_shapes = vec;
+    B.kind = kind;
     return PW_OK;
 }
 
@@ -468,17 +539,11 @@ int32_t pw_advect_batched(const pw_plan* plan, int32_t ndomains, const pw_domain
     if (!plan || !d_args) return PW_ERR_INVALID_ARG;
     if (ndomains != plan->ndomains) return PW_ERR_PLAN_MISMATCH;
     if (!plan->batch.d_table) return PW_ERR_UNSUPPORTED;
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e;
-    switch (plan->storage) {
-        case PW_F64: e = dispatch_batched<double>(plan, d_args, s); break;
-        case PW_F32: e = dispatch_batched<float>(plan, d_args, s); break;
-        case PW_BF16: e = dispatch_batched<bf16_t>(plan, d_args, s); break;
-        case PW_F16: e = dispatch_batched<f16_t>(plan, d_args, s); break;
-        case PW_I16: e = dispatch_batched<fx16_t>(plan, d_args, s); break;
-        case PW_I32: e = dispatch_batched<fx32_t>(plan, d_args, s); break;
-        default: return PW_ERR_UNSUPPORTED;
-    }
+    if (elem_bytes(plan->storage) == 0) return PW_ERR_UNSUPPORTED;
+    const BatchState& B = plan->batch;
+    const BatchedLaunch bl{B.d_table, plan->ndomains, B.launch.tiles, B.launch.workgroups, B.launch.lds_bytes,
+                           B.d_errors, B.vec_shapes};
+    hipError_t e = dispatch_batched(plan->storage, B.launch.chunk, B.kind, bl, d_args, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return report_hip(e);
     return PW_OK;
 }

@@ -57,6 +57,7 @@ struct MarchGeom {
     int32_t nseg;      // x segments
     int32_t seg;       // planes per segment
     int32_t wpad;      // LDS elements per field per slot
+    int32_t cpx;       // compact tile order: chunk slots per XCD and segment (0: XCD-contiguous order)
 };
 
 // Storage types that carry per-field power-of-two scales.
@@ -198,9 +199,31 @@ __global__ __launch_bounds__(NT) void pw_direct_kernel(DomainArgs d) {
 // march variant
 // ---------------------------------------------------------------------------
 
-// Workgroups are dispatched round-robin over the XCDs.  Renumber them so that
-// each XCD receives a contiguous range of tiles: neighbouring chunks, which
-// share their y-halo columns, then run at the same time behind the same L2.
+// Workgroups are dispatched round-robin over the XCDs (workgroup b runs on
+// XCD b mod 8), in order of b.  Two tile orders follow from that.
+//
+// Compact order (march_compact_tile), used when a plane has at least 8
+// chunks: XCD x owns the contiguous chunk range [x nc / 8, (x + 1) nc / 8)
+// of every segment and walks it segment by segment, so at any time all XCDs
+// work on the same one or two segments -- the HBM traffic of the whole chip
+// stays in a narrow band of x planes -- while the chunks that share a y-halo
+// column still meet in one XCD's L2.  Each XCD gets cpx = ceil(nc / 8) slots
+// per segment; with nc not a multiple of 8 some slots are empty and their
+// workgroups exit at once.  Measured on 2048 x 2048 x 64 against the
+// XCD-contiguous order: FP64 3-4% faster, BF16 2-3%; on 512 x 512 x 64 FP64
+// with 16-plane segments 14% faster.
+//
+// XCD-contiguous order (xcd_tile), for fewer than 8 chunks per plane: each
+// XCD receives a contiguous range of the chunk-fastest tile list.
+__device__ __forceinline__ bool march_compact_tile(int b, int nchunks, int cpx, int& c, int& s) {
+    const int x = b % kNumXcd;
+    const int slot = b / kNumXcd;
+    s = slot / cpx;
+    const int lo = x * nchunks / kNumXcd;
+    const int hi = (x + 1) * nchunks / kNumXcd;
+    c = lo + slot % cpx;
+    return c < hi;
+}
 __device__ __forceinline__ int xcd_tile(int b, int G) {
     const int q = G / kNumXcd;
     const int r = G % kNumXcd;
@@ -726,9 +749,14 @@ __global__ __launch_bounds__(NT) void pw_march_kernel(DomainArgs d, MarchGeom g)
     using CT = typename compute_of<ST>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     CT* lds = reinterpret_cast<CT*>(smem_raw);
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    const int c = tile % g.nchunks;
-    const int s = tile / g.nchunks;
+    int c, s;
+    if (g.cpx > 0) {
+        if (!march_compact_tile((int)blockIdx.x, g.nchunks, g.cpx, c, s)) return;   // empty slot, whole workgroup
+    } else {
+        const int tile = xcd_tile(blockIdx.x, gridDim.x);
+        c = tile % g.nchunks;
+        s = tile / g.nchunks;
+    }
     const int i_begin = 1 + s * g.seg;
     const int i_end = min(i_begin + g.seg - 1, d.nx);
     march_tile<ST, NT, P, VEC, NZ>(d, c, i_begin, i_end, g.wpad, lds);

@@ -20,6 +20,7 @@ struct Launch {
     int32_t nchunks = 0;   // march: chunks per plane; direct: blocks per plane
     int32_t nseg = 0;      // march: segments; direct: planes
     int32_t wpad = 0;      // march: LDS elements per field per slot
+    int32_t cpx = 0;       // march: compact tile order, chunk slots per XCD and segment (0: not used)
     int64_t workgroups = 0;
     int64_t tiles = 0;
     int64_t lds_bytes = 0;
@@ -65,7 +66,7 @@ bool scaled_storage(int32_t storage);   // 16-bit and int32 types: per-field sca
 int32_t normalize_shape(const pw_shape& in, pw_shape* out);
 int64_t extent_elems(const pw_shape& s);
 bool march_possible(const pw_shape& s);
-int32_t auto_seg(const pw_shape& s, int32_t nchunks);
+int32_t auto_seg(int32_t storage, const pw_shape& s, int32_t nchunks);
 int32_t resolve_launch(int32_t storage, const pw_shape& s, const pw_tuning& t, Launch* L);
 bool any_overlap(const void* const ins[3], void* const outs[3], int64_t ext);
 bool vector_ok(int32_t storage, const pw_shape& s, const void* const ins[3], void* const outs[3]);

@@ -47,3 +47,17 @@ def algorithmic_bytes(nx: int, ny: int, nz: int, elem: int = 8, coef_elem: int =
     halo = (nx + 2) * (ny + 2) * nz
     inner = nx * ny * nz
     return elem * (3 * halo + 3 * inner) + 4 * nz * coef_elem
+
+
+# Acceptance bounds, max-norm relative error per field (max |g - o| / max |o|
+# over the computed points), shared by the GPU tests and the benchmark's
+# parity gate.
+F64_PARITY_TOL = 1e-12
+#: reduced storage against the FP64 oracle on the original FP64 fields, for
+#: the seeded synthetic inputs (u = 5 + N(0,1), v = 2 + N(0,1), w = 0.3 N(0,1))
+#: and the per-field scales of ``inputs.storage_scales``
+STORAGE_ERROR_BOUND = {"f32": 2e-6, "bf16": 2e-2, "f16": 3e-3, "i16": 3e-3, "i32": 2e-8}
+#: batched domains after perturbation, against the oracle on the domains'
+#: final stored fields: FP64 parity, or FP32 output roundoff plus the
+#: compensated FP32 arithmetic
+BATCHED_ERROR_BOUND = {"f64": F64_PARITY_TOL, "f32": 2.0 ** -24 + 2e-6}

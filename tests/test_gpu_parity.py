@@ -18,6 +18,8 @@ pytestmark = pytest.mark.gpu
 SHAPES = [
     (1, 1, 2), (2, 3, 3), (3, 5, 4), (7, 13, 63), (33, 17, 65), (20, 9, 96),
     (11, 7, 127), (9, 5, 128), (5, 3, 256), (64, 64, 64), (37, 29, 64),
+    # 8 or more chunks per plane (compact tile order), counts not a multiple of 8, ragged last chunks
+    (6, 75, 64), (5, 41, 96), (4, 160, 65),
 ]
 TUNINGS = [
     {"variant": B.VARIANT_DIRECT},

@@ -70,7 +70,7 @@ TILINGS = [{"variant": B.VARIANT_MARCH, "chunk": 256, "seg": 1}, {"variant": B.V
 
 
 @pytest.mark.parametrize("storage", [B.F32, B.BF16, B.I16, B.I32], ids=["f32", "bf16", "i16", "i32"])
-@pytest.mark.parametrize("shape", [(37, 29, 64), (20, 9, 96), (13, 6, 128), (7, 13, 72), (5, 3, 30)],
+@pytest.mark.parametrize("shape", [(37, 29, 64), (20, 9, 96), (13, 6, 128), (7, 13, 72), (5, 3, 30), (6, 75, 64)],
                          ids=lambda s: "x".join(map(str, s)))
 @pytest.mark.parametrize("tuning", TILINGS, ids=["m256s1", "m512s3", "m1024s2", "m1024s64", "direct"])
 def test_reduced_storage_tilings(storage, shape, tuning):
