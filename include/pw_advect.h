@@ -234,6 +234,36 @@ typedef struct pw_domain_args {
 int32_t pw_advect_batched(const pw_plan *plan, int32_t ndomains,
                           const pw_domain_args *d_args, void *stream);
 
+/* pw_advect_batched without a plan, for callers that cannot allocate device
+   memory (code recorded into a HIP graph, tight serving loops, harnesses that
+   forbid hipMalloc): it calls no hipMalloc, hipFree or other allocating
+   routine.  The tile table and error word that a plan would own live in a
+   fixed array of 196,672 bytes per GPU inside the library (allocated with its
+   code, held until the process ends); a small kernel rebuilds the table from
+   the device records on every call, then the batched kernel runs as in
+   pw_advect_batched, with identical results.
+     storage    PW_* storage type.
+     shapes     host array of ndomains shapes (as for pw_advect_plan); the
+                device records must carry the same shapes, checked on the
+                device by a digest: if they differ, no domain is computed and
+                all ndomains are counted as skipped.
+     ndomains   1 .. 4096 (PW_ERR_INVALID_ARG beyond).
+     d_args     device array of ndomains pw_domain_args (as for
+                pw_advect_batched; records are skipped and counted likewise).
+     tuning     host pointer or NULL; chunk, seg and wg_per_cu as for a
+                batched plan.
+     d_skipped  device pointer to one counter or NULL; if given, the number
+                of records this call skipped is added to it (the caller
+                clears it).
+     stream     hipStream_t or NULL.
+   Every call on one GPU uses that GPU's one array: calls that may overlap in
+   time on the same GPU (different streams, different host threads) race and
+   must be ordered by the caller.  Returns PW_ERR_UNSUPPORTED if a shape
+   cannot use the batched kernel. */
+int32_t pw_advect_batched_noalloc(int32_t storage, const pw_shape *shapes, int32_t ndomains,
+                                  const pw_domain_args *d_args, const pw_tuning *tuning,
+                                  unsigned long long *d_skipped, void *stream);
+
 /* Periodic x-y halo fill of u, v, w of every domain of a plan (asynchronous,
    no allocation; may be recorded into a graph).  Each halo column (i, j)
    receives interior column (wrap(i), wrap(j)), wrap(0) = n, wrap(n+1) = 1, so

@@ -66,6 +66,8 @@ SIGNATURES = {
                             c_double, c_double, c_void_p, c_void_p, c_void_p, c_void_p,
                             POINTER(PwScales), c_void_p]),
     "pw_advect_batched": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
+    "pw_advect_batched_noalloc": (c_int32, [c_int32, POINTER(PwShape), c_int32, c_void_p, POINTER(PwTuning),
+                                            c_void_p, c_void_p]),
     "pw_fill_halo_batched": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "pw_perturb_batched": (c_int32, [c_void_p, c_int32, c_void_p, c_uint64, c_void_p, c_double, c_void_p]),
     "pw_plan_error_count": (c_int32, [c_void_p, POINTER(c_ulonglong)]),
@@ -286,6 +288,18 @@ def advect_batched(plan: Plan, d_args, stream=None) -> None:
     """pw_advect_batched; ``d_args`` is a uint8 device tensor holding the pw_domain_args array."""
     check(lib().pw_advect_batched(plan.handle, plan.ndomains, d_args.data_ptr(), stream_handle(stream)),
           "pw_advect_batched")
+
+
+def advect_batched_noalloc(storage: int, shapes: Sequence[PwShape], d_args, tuning=None, d_skipped=None,
+                           stream=None) -> None:
+    """pw_advect_batched_noalloc: the batched call without a plan (nothing is
+    allocated); ``d_skipped`` is an optional int64 device tensor of one element."""
+    arr = (PwShape * len(shapes))(*shapes)
+    t = make_tuning(tuning)
+    check(lib().pw_advect_batched_noalloc(int(storage), arr, len(shapes), d_args.data_ptr(),
+                                          ctypes.byref(t) if t is not None else None,
+                                          d_skipped.data_ptr() if d_skipped is not None else None,
+                                          stream_handle(stream)), "pw_advect_batched_noalloc")
 
 
 def fill_halo_batched(plan: Plan, d_args, stream=None) -> None:

@@ -106,14 +106,21 @@ __device__ __forceinline__ bool aligned16(const void* p) { return (reinterpret_c
 // is not is skipped and counted like a shape mismatch.
 enum BatchKind { kFixedNz = 0, kVector = 1, kAny = 2 };
 
+// gate: NULL, or a device word that must be nonzero for the launch to run
+// (the allocation-free entry point's table check); if it is zero, workgroup
+// 0 counts every domain as skipped and all workgroups exit.
 template <typename ST, int NT, int P, int KIND>
 __global__ __launch_bounds__(NT) void pw_batched_kernel(const BatchDomain* __restrict__ table, int ndom,
                                                         int64_t ntiles, const pw_domain_args* __restrict__ args,
                                                         unsigned long long* errors,
-                                                        int vec_shapes) {
+                                                        int vec_shapes, const uint32_t* gate) {
     using CT = typename compute_of<ST>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     CT* lds = reinterpret_cast<CT*>(smem_raw);
+    if (gate != nullptr && *gate == 0u) {   // uniform over the grid
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(errors, (unsigned long long)ndom);
+        return;
+    }
     // Workgroups are dispatched round-robin over the XCDs.  Give each XCD a
     // contiguous share of the tile range, walked by its own workgroups, so
     // the tiles in flight on one XCD are neighbouring chunks and segments of
@@ -279,6 +286,7 @@ struct BatchedLaunch {
     int64_t workgroups;
     int64_t lds_bytes;
     unsigned long long* errors;
+    const uint32_t* gate;
     bool vec_shapes;
 };
 
@@ -293,7 +301,7 @@ hipError_t launch_batched(const BatchedLaunch& bl, const pw_domain_args* args, h
     });
     if (attr_err != hipSuccess) return attr_err;
     hipLaunchKernelGGL(kern, dim3((unsigned)bl.workgroups), dim3(256), (size_t)bl.lds_bytes, stream, bl.table,
-                       bl.ndomains, bl.tiles, args, bl.errors, bl.vec_shapes ? 1 : 0);
+                       bl.ndomains, bl.tiles, args, bl.errors, bl.vec_shapes ? 1 : 0, bl.gate);
     return hipGetLastError();
 }
 
@@ -542,7 +550,7 @@ int32_t pw_advect_batched(const pw_plan* plan, int32_t ndomains, const pw_domain
     if (elem_bytes(plan->storage) == 0) return PW_ERR_UNSUPPORTED;
     const BatchState& B = plan->batch;
     const BatchedLaunch bl{B.d_table, plan->ndomains, B.launch.tiles, B.launch.workgroups, B.launch.lds_bytes,
-                           B.d_errors, B.vec_shapes};
+                           B.d_errors, nullptr, B.vec_shapes};
     hipError_t e = dispatch_batched(plan->storage, B.launch.chunk, B.kind, bl, d_args, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return report_hip(e);
     return PW_OK;
@@ -614,6 +622,181 @@ int32_t pw_plan_error_count(const pw_plan* plan, unsigned long long* count) {
     *count = 0;
     if (!plan->batch.d_errors) return PW_OK;
     hipError_t e = hipMemcpy(count, plan->batch.d_errors, sizeof(unsigned long long), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return report_hip(e);
+    return PW_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free batched call.  The tile table and the error word live in
+// `scratch`, one array per GPU (file scope, allocated with the code object);
+// a small kernel builds the table from the device records on every call.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace pw {
+namespace {
+
+constexpr int kNoAllocMaxDomains = 4096;
+constexpr int kNoAllocHeader = 64;   // gate word, tile count, error word
+constexpr size_t kNoAllocScratchBytes = kNoAllocHeader + sizeof(BatchDomain) * kNoAllocMaxDomains;   // 196,672 B
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+struct ScratchSlot {
+    std::once_flag once;
+    hipError_t err = hipSuccess;
+    unsigned char* ptr = nullptr;   // device address of this GPU's scratch
+};
+ScratchSlot g_scratch[kMaxDevices];
+
+// Device address of the current GPU's `scratch`, looked up once per device
+// (with that device current).  The host-side symbol is only a stand-in for
+// the device array and must never be passed to a kernel or a copy.
+int32_t scratch_of_current_device(unsigned char** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return report_hip(e);
+    if (dev < 0 || dev >= kMaxDevices) return PW_ERR_UNSUPPORTED;
+    ScratchSlot& sl = g_scratch[dev];
+    std::call_once(sl.once, [&] {
+        void* p = nullptr;
+        sl.err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        sl.ptr = static_cast<unsigned char*>(p);
+    });
+    if (sl.err != hipSuccess) return report_hip(sl.err);
+    if (!sl.ptr) return PW_ERR_HIP;
+    *out = sl.ptr;
+    return PW_OK;
+}
+
+// One term of the shape digest: a hash of (domain index, normalised shape).
+// The digest of a batch is the sum of its terms (mod 2^64), so the device can
+// form it with a parallel reduction and compare it with the host's.
+__host__ __device__ inline uint64_t shape_digest_term(int32_t d, int32_t nx, int32_t ny, int32_t nz, int32_t reserved,
+                                                      int64_t sy, int64_t sx) {
+    uint64_t h = splitmix64(((uint64_t)(uint32_t)d << 32) ^ (uint64_t)(uint32_t)nx);
+    h = splitmix64(h ^ (uint64_t)(uint32_t)ny);
+    h = splitmix64(h ^ ((uint64_t)(uint32_t)nz | ((uint64_t)(uint32_t)reserved << 32)));
+    h = splitmix64(h ^ (uint64_t)sy);
+    return splitmix64(h ^ (uint64_t)sx);
+}
+
+constexpr int kTableThreads = 1024;
+constexpr int kTablePerThread = kNoAllocMaxDomains / kTableThreads;
+
+// Table row of domain d from its record (an empty row if the shape is out of
+// range: the digest of such a batch cannot match a valid one).
+__device__ __forceinline__ BatchDomain record_row(const pw_domain_args* args, int d, int chunk, int seg_max,
+                                                  uint64_t* term) {
+    const pw_shape s = args[d].shape;
+    const int64_t sy = s.sy ? s.sy : s.nz;
+    const int64_t sx = s.sx ? s.sx : (int64_t)(s.ny + 2) * sy;
+    *term = shape_digest_term(d, s.nx, s.ny, s.nz, s.reserved, sy, sx);
+    BatchDomain b{};
+    if (s.nx >= 1 && s.ny >= 1 && s.nz >= 2 && s.nx <= (1 << 30) && (int64_t)s.ny * s.nz < (int64_t(1) << 31))
+        domain_tiles(s.nx, s.ny, s.nz, chunk, seg_max, &b);
+    b.sy = sy;
+    b.sx = sx;
+    return b;
+}
+
+// Builds the tile table of a batch from its device records into scratch (one
+// workgroup): thread t takes domains 4t .. 4t+3, a workgroup scan of the
+// per-thread tile counts gives every domain its first tile, and a reduction
+// forms the shape digest.  The gate word is set only if the digest and the
+// tile total equal the host's, i.e. the records carry the shapes the launch
+// was shaped for.  The error word is cleared.
+__global__ __launch_bounds__(kTableThreads) void pw_noalloc_table_kernel(const pw_domain_args* __restrict__ args,
+                                                                         int ndom, int chunk, int seg_max,
+                                                                         uint64_t digest_host, int64_t tiles_host,
+                                                                         unsigned char* scr) {
+    __shared__ int64_t part[kTableThreads];
+    __shared__ uint64_t hsum[kTableThreads];
+    BatchDomain* table = reinterpret_cast<BatchDomain*>(scr + kNoAllocHeader);
+    const int t = (int)threadIdx.x;
+    int64_t mine = 0;
+    uint64_t h = 0;
+    for (int q = 0; q < kTablePerThread; ++q) {
+        const int d = t * kTablePerThread + q;
+        if (d < ndom) {
+            uint64_t term;
+            const BatchDomain b = record_row(args, d, chunk, seg_max, &term);
+            h += term;
+            mine += (int64_t)b.nchunks * b.nseg;
+        }
+    }
+    part[t] = mine;
+    hsum[t] = h;
+    __syncthreads();
+    // inclusive scan of the tile counts (Hillis-Steele) and tree reduction of
+    // the digest terms into hsum[0]
+    for (int off = 1; off < kTableThreads; off <<= 1) {
+        const int64_t a = t >= off ? part[t - off] : 0;
+        const uint64_t g = (t & (2 * off - 1)) == 0 ? hsum[t + off] : 0;
+        __syncthreads();
+        part[t] += a;
+        hsum[t] += g;
+        __syncthreads();
+    }
+    int64_t first = part[t] - mine;
+    for (int q = 0; q < kTablePerThread; ++q) {
+        const int d = t * kTablePerThread + q;
+        if (d < ndom) {
+            uint64_t term;
+            BatchDomain b = record_row(args, d, chunk, seg_max, &term);
+            b.tile_begin = first;
+            first += (int64_t)b.nchunks * b.nseg;
+            table[d] = b;
+        }
+    }
+    if (t == 0) {
+        const bool ok = hsum[0] == digest_host && part[kTableThreads - 1] == tiles_host;
+        *reinterpret_cast<int64_t*>(scr + 8) = part[kTableThreads - 1];
+        *reinterpret_cast<unsigned long long*>(scr + 16) = 0ull;
+        *reinterpret_cast<uint32_t*>(scr) = ok ? 1u : 0u;
+    }
+}
+
+}  // namespace
+}  // namespace pw
+
+extern "C" {
+
+int32_t pw_advect_batched_noalloc(int32_t storage, const pw_shape* shapes, int32_t ndomains,
+                                  const pw_domain_args* d_args, const pw_tuning* tuning,
+                                  unsigned long long* d_skipped, void* stream) {
+    if (!shapes || !d_args || ndomains < 1) return PW_ERR_INVALID_ARG;
+    if (ndomains > kNoAllocMaxDomains) return PW_ERR_INVALID_ARG;
+    if (elem_bytes(storage) == 0) return PW_ERR_UNSUPPORTED;
+    const pw_tuning t = tuning ? *tuning : pw_tuning{};
+    if (t.variant != PW_VARIANT_AUTO && t.variant != PW_VARIANT_MARCH) return PW_ERR_UNSUPPORTED;
+    // digest of the normalised shapes, then the launch shape; nothing here allocates
+    uint64_t digest = 0;
+    for (int32_t d = 0; d < ndomains; ++d) {
+        pw_shape s;
+        int32_t rc = normalize_shape(shapes[d], &s);
+        if (rc != PW_OK) return rc;
+        digest += shape_digest_term(d, s.nx, s.ny, s.nz, s.reserved, s.sy, s.sx);
+    }
+    Launch L{};
+    int32_t kind = 0;
+    bool vec = false;
+    int32_t rc = batched_launch_shape(storage, shapes, ndomains, t, &L, &kind, &vec);
+    if (rc != PW_OK) return rc;
+    if (L.tiles == 0) return PW_ERR_UNSUPPORTED;
+    unsigned char* scr = nullptr;
+    rc = scratch_of_current_device(&scr);
+    if (rc != PW_OK) return rc;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(pw_noalloc_table_kernel, dim3(1), dim3(kTableThreads), 0, st, d_args, ndomains, L.chunk,
+                       L.seg, digest, L.tiles, scr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return report_hip(e);
+    unsigned long long* errors = d_skipped ? d_skipped : reinterpret_cast<unsigned long long*>(scr + 16);
+    const BatchedLaunch bl{reinterpret_cast<const BatchDomain*>(scr + kNoAllocHeader), ndomains, L.tiles,
+                           L.workgroups, L.lds_bytes, errors, reinterpret_cast<const uint32_t*>(scr), vec};
+    e = dispatch_batched(storage, L.chunk, kind, bl, d_args, st);
     if (e != hipSuccess) return report_hip(e);
     return PW_OK;
 }
