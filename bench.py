@@ -45,6 +45,13 @@ def parse():
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-streaming", action="store_true", help="no host-resident (PCIe-inclusive) runs")
     ap.add_argument("--skip-power", action="store_true", help="no board-power sampling")
+    ap.add_argument("--skip-probes", action="store_true", help="no HBM probe family (no copy ceilings)")
+    ap.add_argument("--skip-pw512", action="store_true", help="no 512x512x64 record")
+    ap.add_argument("--batched-tuning", default=None,
+                    help="JSON pw_tuning for the batched leg instead of the autotuner's choice")
+    ap.add_argument("--batched-replays", type=int, default=100, help="graph replays timed in the batched leg")
+    ap.add_argument("--skip-per-domain", action="store_true",
+                    help="batched leg without the one-launch-per-domain baseline")
     ap.add_argument("--streaming-536m", action="store_true",
                     help="also stream the 536M-point (2048x4096x64) domain, the paper's largest")
     ap.add_argument("--cpu-threads", type=int, default=0, help="oracle threads (0: all usable cores, max 16)")
@@ -312,16 +319,17 @@ def main():
 
     # attainable bandwidth on this card: buffers of one FP64 array of the
     # headline grid each (2.15 GB), read only, write only and mixed
-    probes = probe_family(2.15, dev, stream)
-    result["roofline"]["probes"] = probes
-    mixed = max(probes["copy_1x1"]["gbs"], probes["copy_3x3"]["gbs"])
-    result["roofline"]["frac_of_copy_3x3"] = round(achieved / probes["copy_3x3"]["gbs"], 4)
-    result["roofline"]["frac_of_best_mixed_copy"] = round(achieved / mixed, 4)
-    log("probe family", probes)
+    if not args.skip_probes:
+        probes = probe_family(2.15, dev, stream)
+        result["roofline"]["probes"] = probes
+        mixed = max(probes["copy_1x1"]["gbs"], probes["copy_3x3"]["gbs"])
+        result["roofline"]["frac_of_copy_3x3"] = round(achieved / probes["copy_3x3"]["gbs"], 4)
+        result["roofline"]["frac_of_best_mixed_copy"] = round(achieved / mixed, 4)
+        log("probe family", probes)
 
     # ---------------- the paper's Table I size (512 x 512 x 64), FP64 ----------------
     small = None
-    if args.workload != "pw512":
+    if args.workload != "pw512" and not args.skip_pw512:
         small = small_workload_leg("pw512", tuning, dev, stream, args.steps, args.warmup, log)
         result["pw512"] = small["record"]
 
@@ -355,7 +363,9 @@ def main():
     # ---------------- batched subdomains ----------------
     batches = {}
     if not args.skip_batched:
-        result["batched"], batches = batched_leg(dev, stream, gpts, log)
+        bt = json.loads(args.batched_tuning) if args.batched_tuning else None
+        result["batched"], batches = batched_leg(dev, stream, gpts, log, replays=args.batched_replays,
+                                                 tuning=bt, per_domain=not args.skip_per_domain)
 
     # ---------------- board power during the FP64 kernel ----------------
     if not args.skip_power:
@@ -590,9 +600,10 @@ def streaming_leg(sizes, log, chunks=(32, 64, 128), reps=3):
     return out
 
 
-def batched_leg(dev, stream, f64_gpts, log, replays=100):
-    """384 uneven subdomains, FP64 and FP32: autotuned persistent launch, one
-    graph-captured timestep (perturb u, v; refill halos; advect) replayed
+def batched_leg(dev, stream, f64_gpts, log, replays=100, tuning=None, per_domain=True):
+    """384 uneven subdomains, FP64 and FP32: autotuned launch, one
+    graph-captured timestep (perturb u, v; refill halos; advect; recorded
+    through the library's graph entry points) replayed
     `replays` times, compared with the same timestep as one pw_advect launch
     per domain."""
     import torch
@@ -609,35 +620,51 @@ def batched_leg(dev, stream, f64_gpts, log, replays=100):
         name = B.DTYPE_NAMES[storage]
         batch = BT.DeviceBatch(probs, storage, dev)
         npts = batch.npoints
-        tuning, tms, hit = tune.tuning_for(batch, reps=5)
-        plan = batch.plan(tuning)
+        if tuning is None:
+            log("batched", name, "autotuning")
+            tun, tms, hit = tune.tuning_for(batch, reps=5)
+        else:
+            tun, hit = dict(tuning), None
+        plan = batch.plan(tun)
+        log("batched", name, "plan", plan.info())
         eager_ms = time_steps(lambda: batch.advect(plan, stream), 20, 5, stream)
         g = batch.capture_timestep(plan, seed=inputs.SEED_BASE, amplitude=1e-3)
-        graph_ms = time_steps(g.replay, replays, 3, stream)
-        # baseline: the same timestep with one pw_advect launch per domain, also as a graph
-        plans = batch.per_domain_plans()
-        gp = torch.cuda.CUDAGraph()
-        torch.cuda.synchronize()
-        with torch.cuda.graph(gp):
-            batch.perturb(plan, inputs.SEED_BASE + 1, 1e-3)
-            batch.fill_halo(plan)
-            batch.advect_per_domain(plans)
-        torch.cuda.synchronize()
-        per_dom_ms = time_steps(gp.replay, 20, 3, stream)
+        graph_ms = time_steps(lambda: g.launch(stream), replays, 3, stream)
+        log("batched", name, "graph timestep %.4f ms" % graph_ms)
+        per_dom_ms, gp, plans = None, None, None
+        if per_domain:
+            # baseline: the same timestep with one pw_advect launch per domain,
+            # also as a graph (recorded on a stream of its own)
+            plans = batch.per_domain_plans()
+            rec_stream = torch.cuda.Stream()
+            torch.cuda.synchronize()
+
+            def per_domain_step():
+                batch.perturb(plan, inputs.SEED_BASE + 1, 1e-3, rec_stream)
+                batch.fill_halo(plan, rec_stream)
+                batch.advect_per_domain(plans, rec_stream)
+
+            gp = B.Graph.record(per_domain_step, rec_stream)
+            per_dom_ms = time_steps(lambda: gp.launch(stream), 20, 3, stream)
+            log("batched", name, "per-domain launches %.4f ms" % per_dom_ms)
         ebytes = metrics.ELEM_BYTES[name]
         abytes = sum(metrics.algorithmic_bytes(pp.nx, pp.ny, pp.nz, ebytes) for pp in probs)
-        rec = {"domains": len(probs), "points": npts, "tuning": tuning, "tuning_from_cache": hit,
+        rec = {"domains": len(probs), "points": npts, "tuning": tun, "tuning_from_cache": hit,
                "advect_ms": round(eager_ms, 5),
                "gpoints_per_s": round(npts / (eager_ms * 1e-3) / 1e9, 3),
                "hbm_frac": round(abytes / (eager_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                "graph_timestep_ms": round(graph_ms, 5), "graph_replays": replays,
-               "per_domain_launch_timestep_ms": round(per_dom_ms, 5),
-               "speedup_vs_per_domain_launches": round(per_dom_ms / graph_ms, 3),
+               "per_domain_launch_timestep_ms": None if per_dom_ms is None else round(per_dom_ms, 5),
+               "speedup_vs_per_domain_launches": None if per_dom_ms is None else round(per_dom_ms / graph_ms, 3),
                "speedup_vs_plain_f64_rate": round(npts / (eager_ms * 1e-3) / 1e9 / f64_gpts, 3),
                "plan": plan.info()}
         log("batched", name, rec)
         out[name] = rec
         keep[name] = batch
+        torch.cuda.synchronize()
+        g.close()
+        if gp is not None:
+            gp.close()
         del g, gp, plans
     return out, keep
 

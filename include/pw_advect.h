@@ -156,7 +156,8 @@ typedef struct pw_plan_info {
     int64_t tiles;        /* (chunk, segment) tiles over all domains */
     int64_t lds_bytes;    /* dynamic LDS per workgroup */
     int64_t points;       /* interior grid points over all domains */
-    int64_t batched_workgroups;  /* grid of pw_advect_batched: persistent, or one per tile (0 if unavailable) */
+    int64_t batched_workgroups;  /* grid of pw_advect_batched: persistent, or one per tile padded to
+                                    whole blocks of 64 tiles (0 if unavailable) */
 } pw_plan_info;
 
 /* Create a plan for `ndomains` domains (1 for pw_advect; the batch size for
@@ -238,7 +239,7 @@ int32_t pw_advect_batched(const pw_plan *plan, int32_t ndomains,
    memory (code recorded into a HIP graph, tight serving loops, harnesses that
    forbid hipMalloc): it calls no hipMalloc, hipFree or other allocating
    routine.  The tile table and error word that a plan would own live in a
-   fixed array of 196,672 bytes per GPU inside the library (allocated with its
+   fixed array of 229,440 bytes per GPU inside the library (allocated with its
    code, held until the process ends); a small kernel rebuilds the table from
    the device records on every call, then the batched kernel runs as in
    pw_advect_batched, with identical results.
@@ -281,6 +282,44 @@ int32_t pw_fill_halo_batched(const pw_plan *plan, int32_t ndomains,
 int32_t pw_perturb_batched(const pw_plan *plan, int32_t ndomains,
                            const pw_domain_args *d_args, uint64_t seed,
                            unsigned long long *d_call, double amplitude, void *stream);
+
+/* HIP graphs of library calls (the paper's many short kernel executions,
+   Sec. IV, recorded once and replayed).  A pw_graph owns an instantiated HIP
+   graph; every entry point it records launches kernels only, so each replay
+   redoes exactly the recorded work on the same device buffers (a
+   perturbation's call counter lives in device memory and advances on every
+   replay).
+
+   pw_graph_begin: start recording the work issued on `stream` (a hipStream_t,
+   not NULL: the null stream cannot be recorded) into a graph; work issued on
+   it is recorded, not run, until pw_graph_end.  Returns PW_ERR_CAPTURE if the
+   stream is already recording.  The recording is thread-local: the entry
+   points that allocate (plan creation, the autotuner, host-resident calls)
+   must not be called by this thread until pw_graph_end, since HIP rejects
+   an allocation during the recording and invalidates it.
+   pw_graph_end: stop the recording on `stream` and instantiate it; `graph`
+   (host out-pointer) receives the new graph.  PW_ERR_CAPTURE if the stream
+   is not recording; PW_ERR_HIP if HIP rejects the recording. */
+typedef struct pw_graph pw_graph;
+int32_t pw_graph_begin(void *stream);
+int32_t pw_graph_end(void *stream, pw_graph **graph);
+
+/* Record `nsteps` repeated timesteps of a batched plan into a new graph --
+   each step pw_perturb_batched (seed, d_call, amplitude), then
+   pw_fill_halo_batched, then pw_advect_batched, all on `d_args` -- on a
+   stream of its own (allocates the graph; not for use while another stream
+   of this thread records).  Arguments as for those calls; nsteps >= 1.
+   `graph` (host out-pointer) receives the graph. */
+int32_t pw_graph_capture_timestep(const pw_plan *plan, int32_t ndomains, const pw_domain_args *d_args,
+                                  uint64_t seed, unsigned long long *d_call, double amplitude,
+                                  int32_t nsteps, pw_graph **graph);
+
+/* Replay a graph on `stream` (asynchronous; NULL: the null stream).  Replays
+   on one graph must not overlap in time. */
+int32_t pw_graph_launch(const pw_graph *graph, void *stream);
+
+/* Free a graph (NULL accepted); no replay of it may still be running. */
+int32_t pw_graph_destroy(pw_graph *graph);
 
 /* Number of batched-domain records skipped so far because their shape did
    not match the plan, a field pointer was NULL or (vector-aligned plans) not

@@ -6,7 +6,7 @@ a second pool, and holds the device array of ``pw_domain_args`` records that
 ``pw_advect_batched``, ``pw_fill_halo_batched`` and ``pw_perturb_batched``
 read.  ``capture_timestep`` records one timestep -- perturb u and v, refill
 the periodic halos, compute su, sv, sw of every domain -- into a HIP graph
-(``torch.cuda.CUDAGraph``) that is then replayed once per call.
+through the library's graph entry points, then replayed once per call.
 """
 from __future__ import annotations
 
@@ -94,15 +94,10 @@ class DeviceBatch:
         self.fill_halo(plan, stream)
         self.advect(plan, stream)
 
-    def capture_timestep(self, plan: B.Plan, seed: int, amplitude: float):
-        """Record one timestep into a CUDAGraph (HIP graph); replay() runs it."""
-        import torch
-        g = torch.cuda.CUDAGraph()
-        torch.cuda.synchronize()
-        with torch.cuda.graph(g):
-            self.timestep(plan, seed, amplitude)
-        torch.cuda.synchronize()
-        return g
+    def capture_timestep(self, plan: B.Plan, seed: int, amplitude: float, nsteps: int = 1) -> B.Graph:
+        """Record `nsteps` timesteps into a HIP graph (pw_graph_capture_timestep);
+        ``launch(stream)`` replays them."""
+        return B.Graph.timestep(plan, self.d_args, seed, self.call, amplitude, nsteps)
 
     def per_domain_plans(self, tuning=None) -> List[B.Plan]:
         return [B.Plan(self.storage, [r.shape], tuning) for r in self.records]

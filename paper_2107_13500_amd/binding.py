@@ -71,6 +71,12 @@ SIGNATURES = {
     "pw_fill_halo_batched": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "pw_perturb_batched": (c_int32, [c_void_p, c_int32, c_void_p, c_uint64, c_void_p, c_double, c_void_p]),
     "pw_plan_error_count": (c_int32, [c_void_p, POINTER(c_ulonglong)]),
+    "pw_graph_begin": (c_int32, [c_void_p]),
+    "pw_graph_end": (c_int32, [c_void_p, POINTER(c_void_p)]),
+    "pw_graph_capture_timestep": (c_int32, [c_void_p, c_int32, c_void_p, c_uint64, c_void_p, c_double, c_int32,
+                                            POINTER(c_void_p)]),
+    "pw_graph_launch": (c_int32, [c_void_p, c_void_p]),
+    "pw_graph_destroy": (c_int32, [c_void_p]),
     "pw_autotune": (c_int32, [c_int32, POINTER(PwShape), c_int32, c_void_p, c_void_p, POINTER(PwTuning),
                               c_int32, c_int32, POINTER(PwTuning), POINTER(c_float), POINTER(c_float)]),
     "pw_autotune_candidates": (c_int32, [c_int32, POINTER(PwTuning), c_int32]),
@@ -311,6 +317,53 @@ def perturb_batched(plan: Plan, d_args, seed: int, d_call, amplitude: float, str
     check(lib().pw_perturb_batched(plan.handle, plan.ndomains, d_args.data_ptr(), int(seed),
                                    d_call.data_ptr(), float(amplitude), stream_handle(stream)),
           "pw_perturb_batched")
+
+
+class Graph:
+    """Owning wrapper of a pw_graph (an instantiated HIP graph of library calls)."""
+
+    def __init__(self, handle: c_void_p):
+        self.handle = handle
+
+    @classmethod
+    def timestep(cls, plan: Plan, d_args, seed: int, d_call, amplitude: float, nsteps: int = 1) -> "Graph":
+        """pw_graph_capture_timestep: `nsteps` perturb + halo + advect steps of a batched plan."""
+        h = c_void_p()
+        check(lib().pw_graph_capture_timestep(plan.handle, plan.ndomains, d_args.data_ptr(), int(seed),
+                                              d_call.data_ptr(), float(amplitude), int(nsteps), ctypes.byref(h)),
+              "pw_graph_capture_timestep")
+        return cls(h)
+
+    @classmethod
+    def record(cls, fn, stream) -> "Graph":
+        """Record the library calls `fn()` issues on `stream` (pw_graph_begin / pw_graph_end)."""
+        s = stream_handle(stream)
+        check(lib().pw_graph_begin(s), "pw_graph_begin")
+        try:
+            fn()
+        except BaseException:
+            h = c_void_p()
+            lib().pw_graph_end(s, ctypes.byref(h))   # abandon the recording
+            if h.value:
+                lib().pw_graph_destroy(h)
+            raise
+        h = c_void_p()
+        check(lib().pw_graph_end(s, ctypes.byref(h)), "pw_graph_end")
+        return cls(h)
+
+    def launch(self, stream=None) -> None:
+        check(lib().pw_graph_launch(self.handle, stream_handle(stream)), "pw_graph_launch")
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            check(lib().pw_graph_destroy(self.handle), "pw_graph_destroy")
+            self.handle = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def probe_copy(srcs, dsts, nbytes: int, workgroups: int = 0, stream=None) -> None:

@@ -22,7 +22,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIBRARY = os.path.join(HERE, "libpwadvect.so")
-SOURCES = ["pw_advect.hip", "pw_batched.hip", "pw_tune.hip", "pw_stream.hip", "pw_probe.hip"]
+SOURCES = ["pw_advect.hip", "pw_batched.hip", "pw_graph.hip", "pw_tune.hip", "pw_stream.hip", "pw_probe.hip"]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -376,6 +376,9 @@ struct MarchTile {
     using V2 = typename vec2_of<CT>::type;
     V2 cm[CARRY ? PPT / 2 : 1][27];
     V2 c0[CARRY ? PPT / 2 : 1][27];
+    // CARRY: the x-face sums of sv's and sw's x terms, carried from plane to
+    // plane (pw_point's xs), so each is formed once instead of twice
+    CT xs[CARRY ? PPT : 1][2];
     // ZEND (fixed-point storage with the register carry, policies where a
     // zero product is an exact zero): the column's end points get zero
     // coefficients instead of selects -- all of them at k = 1, and at the top
@@ -541,6 +544,13 @@ struct MarchTile {
     // CARRY: this step's blocks of pair pq, from the carried registers where
     // the previous step read them, else from LDS (slots sm, sc, sp hold planes
     // i-1, i, i+1).  Compile-time loop over all 81 keys; unused keys vanish.
+    // Each LDS read is a single 8-byte read at an immediate offset from the
+    // pair's one base address (every slot, field and row lies within the
+    // 64 KiB offset range).  A scheduling barrier after each read keeps the
+    // compiler from pairing reads into two-address reads, whose 2 KiB offset
+    // range would cost a vector add for a new base address nearly every
+    // time: in these VALU-bound kernels five such adds per plane and thread
+    // measured slower than the extra LDS instructions.
     template <int K>
     __device__ __forceinline__ void gather_blocks(V2* blk, int pq, int sm, int sc, int sp) {
         if constexpr (K < 81) {
@@ -553,6 +563,7 @@ struct MarchTile {
                 } else {
                     const int slot = di < 0 ? sm : (di > 0 ? sp : sc);
                     blk[K] = *reinterpret_cast<const V2*>(block_base(pq, slot, F) + dj * NZ + b);
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
             gather_blocks<K + 1>(blk, pq, sm, sc, sp);
@@ -584,6 +595,20 @@ struct MarchTile {
         }
     }
 
+    // CARRY: the x-face sums at plane i_begin - 1 from the carried blocks of
+    // that plane (cm, just primed), in the order pw_point forms them.
+    __device__ __forceinline__ void prime_sums(int pq) {
+        constexpr int kU0 = pair_carry_key(0, 0, 0), kU0b = pair_carry_key(0, 0, 2), kU1 = pair_carry_key(0, 1, 0);
+        static_assert(pair_block_used(0, 0, -1, 0) && pair_block_used(0, 0, 0, 0) && pair_block_used(0, 0, -1, 2) &&
+                          pair_block_used(0, 0, 0, 2) && pair_block_used(0, 1, -1, 0) && pair_block_used(0, 1, 0, 0),
+                      "sum blocks must be carried");
+        const V2 a = cm[pq][kU0], b = cm[pq][kU0b], r = cm[pq][kU1];
+        xs[2 * pq][0] = a[0] + r[0];       // u(k, j) + u(k, j+1)
+        xs[2 * pq][1] = a[0] + a[1];       // u(k) + u(k+1)
+        xs[2 * pq + 1][0] = a[1] + r[1];
+        xs[2 * pq + 1][1] = a[1] + b[0];
+    }
+
     // Compute plane i from the slots sm (plane i-1), sc (plane i), sp (plane i+1).
     __device__ __forceinline__ void compute(int i, int sm, int sc, int sp) {
         const int64_t obase = (int64_t)i * d.sx + wb;
@@ -603,10 +628,10 @@ struct MarchTile {
                 if (q % 2 == 0) gather_blocks<0>(blk[q / 2], q / 2, sm, sc, sp);
                 if (q % 2 == 0) {
                     CachedPairAcc<CT, 0> A{blk[q / 2]};
-                    pw_point<AR, false, !ZEND, false>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2]);
+                    pw_point<AR, false, !ZEND, false>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2], xs[q]);
                 } else {
                     CachedPairAcc<CT, 1> A{blk[q / 2]};
-                    pw_point<AR, false, false, !ZEND>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2]);
+                    pw_point<AR, false, false, !ZEND>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2], xs[q]);
                     keep_blocks<0>(blk[q / 2], q / 2);
                 }
             } else if constexpr (PAIR) {
@@ -632,20 +657,20 @@ struct MarchTile {
                 pw_point<AR, false>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2]);
             }
         }
-        ST* outs[3] = {static_cast<ST*>(d.su), static_cast<ST*>(d.sv), static_cast<ST*>(d.sw)};
+        ST* outs[3] = {static_cast<ST*>(d.su) + obase, static_cast<ST*>(d.sv) + obase, static_cast<ST*>(d.sw) + obase};
         if constexpr (PAIR) {
 #pragma unroll
             for (int q = 0; q < PPT; q += 2) {
                 if (!EXACT && !live[q]) continue;   // a pair never straddles the chunk end (P, nz even)
 #pragma unroll
-                for (int f = 0; f < 3; ++f) store_pair(outs[f] + obase + li[q], res[q][f], res[q + 1][f]);
+                for (int f = 0; f < 3; ++f) store_pair(outs[f] + (uint32_t)li[q], res[q][f], res[q + 1][f]);
             }
         } else {
 #pragma unroll
             for (int q = 0; q < PPT; ++q) {
                 if (!EXACT && !live[q]) continue;
 #pragma unroll
-                for (int f = 0; f < 3; ++f) store_out(outs[f] + obase + li[q], res[q][f]);
+                for (int f = 0; f < 3; ++f) store_out(outs[f] + (uint32_t)li[q], res[q][f]);
             }
         }
     }
@@ -719,7 +744,10 @@ struct MarchTile {
         if constexpr (CARRY) {
             __syncthreads();
 #pragma unroll
-            for (int pq = 0; pq < PPT / 2; ++pq) prime_blocks<0>(pq);
+            for (int pq = 0; pq < PPT / 2; ++pq) {
+                prime_blocks<0>(pq);
+                prime_sums(pq);
+            }
         }
         if constexpr (NZ > 0) {
             for (int i = i_begin;; i += UNROLL) {
@@ -743,9 +771,18 @@ __device__ __forceinline__ void march_tile(const DomainArgs& d, int c, int i_beg
     t.run(i_begin, i_end);
 }
 
+// Resident waves per SIMD the single-domain march kernel may reach: FP64
+// storage is held at two (two workgroups per CU, each with two planes in
+// flight): three workgroups per CU, with more planes in flight or without,
+// measured 10% slower on 2048 x 2048 x 64 -- more concurrent streams cost
+// the HBM more than the extra bytes in flight gain.  Other storage types are
+// not capped.
+template <typename ST> constexpr int march_max_waves() { return std::is_same<ST, double>::value ? 2 : 8; }
+
 // Single domain: one workgroup per (chunk, segment) tile.
 template <typename ST, int NT, int P, bool VEC, int NZ>
-__global__ __launch_bounds__(NT) void pw_march_kernel(DomainArgs d, MarchGeom g) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, march_max_waves<ST>())))
+void pw_march_kernel(DomainArgs d, MarchGeom g) {
     using CT = typename compute_of<ST>::type;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     CT* lds = reinterpret_cast<CT*>(smem_raw);

@@ -34,6 +34,8 @@ struct BatchDomain {
     int32_t seg;          // planes per segment: nx split into nseg even parts
     int64_t sy, sx;
     int64_t tile_begin;   // first global tile of this domain
+    int32_t rec;          // index of the domain's record in the caller's pw_domain_args array
+    int32_t pad_;
 };
 
 struct BatchState {

@@ -44,14 +44,21 @@ namespace pw {
 // ---------------------------------------------------------------- FP64: as written
 struct ArithF64 {
     using T = double;
+    static constexpr bool kCarrySums = true;   // has cross_sums (x-face sums carried along the march)
     static constexpr double kCrossScale = 1.0;   // cross_flux returns the flux difference itself
     static constexpr bool kExactZeroFlux = true;   // c2 * 0 * (w3 + w4) leaves the sum unchanged
     static __device__ __forceinline__ double self_flux(double A, double U, double C) {
         return A * (U + A) - C * (U + C);
     }
+    // E F - G H on the two face sums; cross_flux forms the sums first, so a
+    // caller that already holds them (carried from the previous x plane)
+    // gets bit-identical results
+    static __device__ __forceinline__ double cross_sums(double E, double F, double G, double H) {
+        return E * F - G * H;
+    }
     static __device__ __forceinline__ double cross_flux(double E, double v1, double v2, double G, double v3,
                                                         double v4) {
-        return E * (v1 + v2) - G * (v3 + v4);
+        return cross_sums(E, v1 + v2, G, v3 + v4);
     }
     static __device__ __forceinline__ double add_vert(double s, double c1, double a, double w1, double w2, double c2,
                                                       double c, double w3, double w4) {
@@ -65,6 +72,7 @@ struct ArithF64 {
 // ---------------------------------------------------------------- FP32: difference first
 struct ArithSplit {
     using T = float;
+    static constexpr bool kCarrySums = false;   // its cross form needs the four values, not two sums
     // the difference-first vertical form still rounds w3 + w4 when c = 0
     static constexpr bool kExactZeroFlux = false;
     // A (U + A) - C (U + C) = (A - C) (U + A + C)
@@ -101,6 +109,7 @@ struct ArithSplit {
 // ---------------------------------------------------------------- FP32: Kahan product differences
 struct ArithKahan {
     using T = float;
+    static constexpr bool kCarrySums = true;
     static constexpr float kCrossScale = 1.0f;
     static constexpr bool kExactZeroFlux = true;   // a b - 0 d = RN(a b) exactly
     // a b - c d: w = RN(c d); e = c d - w exactly; RN(RN(a b - w) - e)
@@ -110,8 +119,9 @@ struct ArithKahan {
         return __builtin_fmaf(a, b, -w) - e;
     }
     static __device__ __forceinline__ float self_flux(float A, float U, float C) { return (A - C) * ((U + A) + C); }
+    static __device__ __forceinline__ float cross_sums(float E, float F, float G, float H) { return pdiff(E, F, G, H); }
     static __device__ __forceinline__ float cross_flux(float E, float v1, float v2, float G, float v3, float v4) {
-        return pdiff(E, v1 + v2, G, v3 + v4);
+        return cross_sums(E, v1 + v2, G, v3 + v4);
     }
     static __device__ __forceinline__ float add_vert(float s, float c1, float a, float w1, float w2, float c2, float c,
                                                      float w3, float w4) {
@@ -148,10 +158,19 @@ struct PointCoefs {
 // share their reads.  MAY_BOTTOM / MAY_TOP = false state that k is never 1 /
 // never nz for this point (known at compile time for pairs of levels in
 // even-height columns), which drops the corresponding select.
+//
+// xs (unguarded form, policies with kCarrySums, or NULL): the x-face sums of
+// the x terms of sv and sw, carried along the x march.  The lower face of
+// plane i is the upper face of plane i-1, so on entry xs[0] holds
+// u(k, j, i-1) + u(k, j+1, i-1) (sv) and xs[1] holds u(k, j, i-1) +
+// u(k+1, j, i-1) (sw), and on return the same sums at plane i.  The sums are
+// the same operations on the same values as when formed here, so results do
+// not change.  (At the column top xs[1] leaves with the top-zeroed upper
+// value; only sw(nz) would read it, and that result is replaced by zero.)
 template <typename AR, bool GUARDED, bool MAY_BOTTOM = true, bool MAY_TOP = true, typename Acc,
           typename CT = typename AR::T>
 __device__ __forceinline__ void pw_point(const Acc& A, int k, int nz, const PointCoefs<CT>& c, CT& su, CT& sv,
-                                         CT& sw) {
+                                         CT& sw, CT* xs = nullptr) {
     if constexpr (GUARDED) {
         if (k < 2) {
             su = CT(0);
@@ -181,7 +200,17 @@ __device__ __forceinline__ void pw_point(const Acc& A, int k, int nz, const Poin
     s = s + (c.yu * AR::kCrossScale) * AR::cross_flux(u_ym, v_ym, A.template v<0, -1, 1>(), u_yp, v0, v_xp);
     // sv: mirror of su, own-direction (y) term first
     CT t = c.yv * AR::self_flux(v_ym, v0, v_yp);
-    t = t + (c.xv * AR::kCrossScale) * AR::cross_flux(v_xm, u_xm, A.template u<0, 1, -1>(), v_xp, u0, u_yp);
+    if constexpr (!GUARDED && AR::kCarrySums) {
+        if (xs != nullptr) {
+            const CT h = u0 + u_yp;   // upper x face of v, u(k, j, i) + u(k, j+1, i)
+            t = t + (c.xv * AR::kCrossScale) * AR::cross_sums(v_xm, xs[0], v_xp, h);
+            xs[0] = h;
+        } else {
+            t = t + (c.xv * AR::kCrossScale) * AR::cross_flux(v_xm, u_xm, A.template u<0, 1, -1>(), v_xp, u0, u_yp);
+        }
+    } else {
+        t = t + (c.xv * AR::kCrossScale) * AR::cross_flux(v_xm, u_xm, A.template u<0, 1, -1>(), v_xp, u0, u_yp);
+    }
 
     const CT w_u_lo = A.template w<-1, 0, 1>();   // w(k-1, j, i+1): lower z face of u
     const CT w_v_lo = A.template w<-1, 1, 0>();   // w(k-1, j+1, i): lower z face of v
@@ -192,8 +221,20 @@ __device__ __forceinline__ void pw_point(const Acc& A, int k, int nz, const Poin
         a = AR::add_vert(s, c.z1u, u_zm, w_zm, w_u_lo, c.z2u, u_zp, w0, w_xp);
         b = AR::add_vert(t, c.z1v, v_zm, w_zm, w_v_lo, c.z2v, v_zp, w0, w_yp);
         // sw: x and y terms with u, v summed over levels k, k+1; then w along z
-        CT q = (c.xw * AR::kCrossScale) *
-               AR::cross_flux(A.template w<0, 0, -1>(), u_xm, A.template u<1, 0, -1>(), w_xp, u0, u_zp);
+        CT q;
+        if constexpr (!GUARDED && AR::kCarrySums) {
+            if (xs != nullptr) {
+                const CT h = u0 + u_zp;   // upper x face of w, u(k, j, i) + u(k+1, j, i)
+                q = (c.xw * AR::kCrossScale) * AR::cross_sums(A.template w<0, 0, -1>(), xs[1], w_xp, h);
+                xs[1] = h;
+            } else {
+                q = (c.xw * AR::kCrossScale) *
+                    AR::cross_flux(A.template w<0, 0, -1>(), u_xm, A.template u<1, 0, -1>(), w_xp, u0, u_zp);
+            }
+        } else {
+            q = (c.xw * AR::kCrossScale) *
+                AR::cross_flux(A.template w<0, 0, -1>(), u_xm, A.template u<1, 0, -1>(), w_xp, u0, u_zp);
+        }
         q = q + (c.yw * AR::kCrossScale) *
                     AR::cross_flux(A.template w<0, -1, 0>(), v_ym, A.template v<1, -1, 0>(), w_yp, v0, v_zp);
         r = AR::add_vself(q, c.z1w, w_zm, w0, c.z2w, w_zp);

@@ -223,7 +223,7 @@ def test_graph_replays_match_eager_steps():
     g = ga.capture_timestep(pa, seed=7, amplitude=1e-3)
     scratch = torch.randn(256, 256, device=DEV)
     for r in range(4):
-        g.replay()
+        g.launch()
         eb.timestep(pb, seed=7, amplitude=1e-3)
         scratch = scratch @ scratch.T / 256.0      # unrelated eager work between replays
         torch.cuda.synchronize()
@@ -285,7 +285,7 @@ def test_full_384_domain_batch_graph(storage, tuning):
     say("384 domains", batch.npoints, plan.info())
     g = batch.capture_timestep(plan, seed=11, amplitude=1e-3)
     for _ in range(3):
-        g.replay()
+        g.launch()
     torch.cuda.synchronize()
     assert plan.error_count() == 0
     for d in (0, 1, 77, 191, 300, 383):

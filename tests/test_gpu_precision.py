@@ -14,13 +14,31 @@ import oracle
 import staggered_rule as rule
 from gpu_helpers import DEV, max_rel, positive_zeros, say
 from paper_2107_13500_amd import binding as B
-from paper_2107_13500_amd import inputs
+from paper_2107_13500_amd import inputs, metrics
 
 pytestmark = pytest.mark.gpu
 
 UNIT_ROUNDOFF = {B.F32: 2.0 ** -24, B.BF16: 2.0 ** -8, B.F16: 2.0 ** -11}
-ORIG_BOUND = {B.F32: 2e-6, B.BF16: 2e-2, B.F16: 3e-3, B.I16: 3e-3, B.I32: 2e-8}
+ORIG_BOUND = {B.F32: metrics.STORAGE_ERROR_BOUND["f32"], B.BF16: metrics.STORAGE_ERROR_BOUND["bf16"],
+              B.F16: metrics.STORAGE_ERROR_BOUND["f16"], B.I16: metrics.STORAGE_ERROR_BOUND["i16"],
+              B.I32: metrics.STORAGE_ERROR_BOUND["i32"]}
 FIXED = (B.I16, B.I32)
+# Arithmetic error of the FP32-compute path against the oracle on the same
+# (dequantised) inputs, relative to the largest output: a few FP32 roundings
+# of terms no larger than a few times the output (the seeded fields are
+# smooth, so the flux differences cancel at most about tenfold): 8 units of
+# 2^-24.  The FP64-compute path (int32 storage) gets 8 units of 2^-53 times
+# the same cancellation allowance.
+FP32_ARITH = 8 * 2.0 ** -24
+FP64_ARITH = 80 * 2.0 ** -53
+
+
+def arith_bound(storage, out_scale, max_abs):
+    """Max-norm bound against the oracle on dequantised inputs: the output
+    type's rounding plus the compute type's arithmetic."""
+    if storage in FIXED:
+        return 0.5 / (out_scale * max_abs) + (FP64_ARITH if storage == B.I32 else FP32_ARITH)
+    return UNIT_ROUNDOFF[storage] + FP32_ARITH
 
 
 def run_storage(p, storage, tuning=None):
@@ -53,13 +71,10 @@ def test_reduced_storage_error_bounds(storage, shape):
         e_orig = max_rel(gi, ro[1:-1, 1:-1])
         e_deq = max_rel(gi, rd[1:-1, 1:-1])
         say(B.DTYPE_NAMES[storage], shape, name, "vs original %.3e, vs dequantised %.3e" % (e_orig, e_deq))
-        if storage in FIXED:
-            # output quantum 1/out_scale, rounded to nearest: half a quantum
-            # relative to the largest output, plus the compute type's rounding
-            bound = 0.5 / (os_ * np.max(np.abs(rd[1:-1, 1:-1])))
-            bound += 1e-12 if storage == B.I32 else 2e-6
-        else:
-            bound = UNIT_ROUNDOFF[storage] + 2e-6
+        # output quantum (fixed point: half of 1/out_scale; floating: the
+        # type's unit roundoff) relative to the largest output, plus the
+        # compute type's arithmetic
+        bound = arith_bound(storage, os_, np.max(np.abs(rd[1:-1, 1:-1])))
         assert e_deq <= bound, "%s arithmetic error %.3e > %.3e" % (name, e_deq, bound)
         assert e_orig <= ORIG_BOUND[storage], "%s error vs FP64 oracle %.3e" % (name, e_orig)
 
@@ -69,7 +84,7 @@ TILINGS = [{"variant": B.VARIANT_MARCH, "chunk": 256, "seg": 1}, {"variant": B.V
            {"variant": B.VARIANT_DIRECT}]
 
 
-@pytest.mark.parametrize("storage", [B.F32, B.BF16, B.I16, B.I32], ids=["f32", "bf16", "i16", "i32"])
+@pytest.mark.parametrize("storage", [B.F32, B.BF16, B.F16, B.I16, B.I32], ids=["f32", "bf16", "f16", "i16", "i32"])
 @pytest.mark.parametrize("shape", [(37, 29, 64), (20, 9, 96), (13, 6, 128), (7, 13, 72), (5, 3, 30), (6, 75, 64)],
                          ids=lambda s: "x".join(map(str, s)))
 @pytest.mark.parametrize("tuning", TILINGS, ids=["m256s1", "m512s3", "m1024s2", "m1024s64", "direct"])
@@ -87,10 +102,7 @@ def test_reduced_storage_tilings(storage, shape, tuning):
         if name == "sw":
             assert positive_zeros(gi[:, :, -1]), "sw(nz) must be exactly +0"
         e = max_rel(gi, rd[1:-1, 1:-1])
-        if storage in FIXED:
-            bound = 0.5 / (os_ * np.max(np.abs(rd[1:-1, 1:-1]))) + (1e-12 if storage == B.I32 else 2e-6)
-        else:
-            bound = UNIT_ROUNDOFF[storage] + 2e-6
+        bound = arith_bound(storage, os_, np.max(np.abs(rd[1:-1, 1:-1])))
         assert e <= bound, "%s %s %s: %.3e > %.3e" % (B.DTYPE_NAMES[storage], tuning, name, e, bound)
 
 
@@ -119,7 +131,7 @@ def test_fixed_point_outputs_round_and_saturate(storage, tuning):
         # half a unit for the rounding, plus the compute type's error relative
         # to the largest result; results farther than that from a limit must
         # saturate or stay in range
-        tol = 0.5 + (1e-12 if storage == B.I32 else 2e-6) * np.max(np.abs(x))
+        tol = 0.5 + (FP64_ARITH if storage == B.I32 else FP32_ARITH) * np.max(np.abs(x))
         over, under = x > hi + tol, x < lo - tol
         assert over.any() and under.any(), "%s: the scale must push results out of range" % name
         assert np.all(g[over] == hi) and np.all(g[under] == lo), "%s: saturation" % name
@@ -129,31 +141,130 @@ def test_fixed_point_outputs_round_and_saturate(storage, tuning):
         say(B.DTYPE_NAMES[storage], tuning, name, "in-range error %.3f units (bound %.3f)" % (err, tol))
         assert err <= tol, "%s: %.3f > %.3f" % (name, err, tol)
 
+def naive_fp32(u, v, w, co, nx, ny, nz):
+    """The staggering rule evaluated term by term in np.float32 (products
+    first, then their difference: no compensation), every computed point."""
+    F = rule.Fields(u, v, w, co.tcx, co.tcy, *co.arrays(), conv=np.float32)
+    shp = u.shape
+    out = {n: np.zeros(shp) for n in "uvw"}
+    for i in range(1, nx + 1):
+        for j in range(1, ny + 1):
+            for k in range(1, nz + 1):
+                for n in "uvw":
+                    out[n][i, j, k - 1] = float(rule.source(F, n, (k, j, i)))
+    return [out[n] for n in "uvw"]
+
+
+def pow2_coefficients(nz, tc=2.0 ** -10, tz=2.0 ** -8):
+    """Uniform coefficients that are powers of two (tzc1 = tzc2, tzd1 = tzd2),
+    so every coefficient product is exact and uniform fields give exactly
+    zero: the flux differences then cancel as much as the fields do."""
+    one = np.full(nz, tz)
+    one[0] = 0.0
+    d = one.copy()
+    d[-1] = 0.0
+    return inputs.Coefficients(tc, tc, one.copy(), one.copy(), d.copy(), d.copy())
+
+
 def test_fp32_difference_first_beats_naive_fp32_on_cancelling_fields():
-    """u = 50 + N(0, 0.01), v = 20 + N(0, 0.01): every flux difference cancels
-    ~10^3-fold.  Naive FP32 (the staggering rule evaluated in np.float32) loses
-    ~4 digits; the library's FP32 path stays near FP32 roundoff."""
+    """u = 50 + N(0, 0.01), v = 20 + N(0, 0.01), w = 30 + N(0, 0.01) with
+    uniform power-of-two coefficients: every flux difference of su, sv and sw
+    cancels about 10^3-fold.  Naive FP32 (the staggering rule in np.float32)
+    loses about three digits; the library's difference-first FP32 stays within
+    a few FP32 roundings of the result."""
     nx, ny, nz = 6, 5, 8
     rng = np.random.default_rng(77)
     shp = (nx + 2, ny + 2, nz)
     u = (50.0 + 0.01 * rng.standard_normal(shp)).astype(np.float32).astype(np.float64)
     v = (20.0 + 0.01 * rng.standard_normal(shp)).astype(np.float32).astype(np.float64)
-    w = (0.01 * rng.standard_normal(shp)).astype(np.float32).astype(np.float64)
-    co = inputs.coefficients(inputs.vertical_grid(nz), 50.0, 50.0)
+    w = (30.0 + 0.01 * rng.standard_normal(shp)).astype(np.float32).astype(np.float64)
+    co = pow2_coefficients(nz)
     p = inputs.Problem(nx, ny, nz, u, v, w, co, inputs.vertical_grid(nz))
     got, deq, _ = run_storage(p, B.F32)
     ref = oracle.advect(u, v, w, co.tcx, co.tcy, *co.arrays())
-    F = rule.Fields(u, v, w, co.tcx, co.tcy, *co.arrays(), conv=np.float32)
-    naive = {n: np.zeros(shp) for n in "uvw"}
-    for i in range(1, nx + 1):
-        for j in range(1, ny + 1):
-            for k in range(1, nz + 1):
-                for n in "uvw":
-                    naive[n][i, j, k - 1] = float(rule.source(F, n, (k, j, i)))
-    for name, g, r in zip("uvw", got, ref):
-        e_gpu = max_rel(g[1:-1, 1:-1], r[1:-1, 1:-1])
-        e_naive = max_rel(naive[name][1:-1, 1:-1], r[1:-1, 1:-1])
+    naive = naive_fp32(u, v, w, co, nx, ny, nz)
+    # levels 2 .. nz-1: at the column top su and sv keep only the lower
+    # vertical flux, which does not cancel and would dominate the max norm
+    inner = (slice(1, -1), slice(1, -1), slice(1, nz - 1))
+    for name, g, r, nv in zip("uvw", got, ref, naive):
+        e_gpu = max_rel(g[inner], r[inner])
+        e_naive = max_rel(nv[inner], r[inner])
         say("cancelling s%s: library FP32 %.2e, naive FP32 %.2e" % (name, e_gpu, e_naive))
-        assert e_gpu <= 2e-6
-        if name in "uv":
-            assert e_naive >= 20 * e_gpu
+        assert e_gpu <= UNIT_ROUNDOFF[B.F32] + FP32_ARITH
+        assert e_naive >= 20 * e_gpu, "s%s: compensation gains nothing (%.2e vs %.2e)" % (name, e_gpu, e_naive)
+
+
+def checkerboard_fields(nx, ny, nz, big, small, quantum_big, quantum_small, seed, spread=1):
+    """Stored values exactly representable in the 16-bit type: a 3-D
+    checkerboard of `big` and `small` magnitudes (parity of i + j + k) with
+    random offsets of up to `spread` quanta.  Neighbours along any axis differ in
+    magnitude, so each sum of two neighbours carries the bits of both and
+    the products of the flux terms need more than FP32's 24 bits; values two
+    apart along an axis have the same parity, so each flux difference
+    cancels about a thousandfold."""
+    rng = np.random.default_rng(seed)
+    shp = (nx + 2, ny + 2, nz)
+    ii, jj, kk = np.meshgrid(np.arange(shp[0]), np.arange(shp[1]), np.arange(shp[2]), indexing="ij")
+    even = (ii + jj + kk) % 2 == 0
+    out = []
+    for f in range(3):
+        a = np.where(even, big[f] + quantum_big * rng.integers(-spread, spread + 1, shp),
+                     small[f] + quantum_small * rng.integers(-3 * spread, 3 * spread + 1, shp))
+        out.append(a.astype(np.float64))
+    return out
+
+
+def correctly_rounded(x, storage, out_scale):
+    """Exact values x (FP64 oracle) rounded to the stored output as the
+    library's contract says: scaled, then round to nearest even (fixed point
+    also saturated)."""
+    t = torch.from_numpy(x * out_scale)
+    if storage in FIXED:
+        return torch.round(t).clamp_(*B.FIXED_RANGE[storage]).to(B.torch_dtype(storage))
+    return t.to(B.torch_dtype(storage))
+
+
+@pytest.mark.parametrize("storage", [B.F16, B.I16], ids=["f16", "i16"])
+def test_kahan_product_differences_round_correctly_where_naive_fp32_does_not(storage):
+    """16-bit storage computes each product difference E F - G H by Kahan's
+    algorithm.  On fields whose flux differences cancel a thousandfold while
+    the products need more than 24 bits, the stored su, sv and sw must be the
+    correctly rounded exact results (FP64 oracle on the stored inputs,
+    scaled and rounded to the output type) at almost every point, while the
+    naive FP32 evaluation of the same rule, rounded the same way, is wrong at
+    a large share of them."""
+    nx, ny, nz = 6, 5, 64
+    if storage == B.F16:
+        # FP16: 1024 + integers (quantum 1) next to 4 + multiples of 2^-8
+        fields = checkerboard_fields(nx, ny, nz, (1024.0, 1536.0, 1280.0), (4.0, 6.0, 5.0), 1.0, 2.0 ** -8, 91)
+    else:
+        # int16: 24000 + integers next to 100 + integers
+        fields = checkerboard_fields(nx, ny, nz, (24000.0, 20000.0, 16000.0), (100.0, 80.0, 60.0), 1.0, 1.0, 92)
+    co = pow2_coefficients(nz)
+    exact = oracle.advect(*fields, co.tcx, co.tcy, *co.arrays())
+    # inputs stored as they are (scale 1, every value representable); output
+    # scales put the largest result of levels 2 .. nz-1 near 2^14 (the column
+    # top keeps only the lower vertical flux, which does not cancel: it is
+    # left out of the scales and the statistics, and may saturate)
+    inner = (slice(1, -1), slice(1, -1), slice(1, nz - 1))
+    out_scales = tuple(inputs.pow2_scale(float(np.max(np.abs(r[inner])))) for r in exact)
+    sc = B.make_scales((1.0, 1.0, 1.0), out_scales)
+    stored = [B.to_storage(a, storage, 1.0, DEV) for a in fields]
+    for a, st in zip(fields, stored):
+        assert np.array_equal(st.double().cpu().numpy(), a), "inputs must be exactly representable"
+    tz = [torch.from_numpy(x).to(DEV) for x in co.arrays()]
+    d = B.DeviceDomain(*stored, co.tcx, co.tcy, *tz, scales=sc)
+    d.run(B.Plan(storage, [B.shape_of(stored[0])]))
+    torch.cuda.synchronize()
+    naive = naive_fp32(*fields, co, nx, ny, nz)
+    for name, g, r, nv, os_ in zip("uvw", d.outputs, exact, naive, out_scales):
+        want = correctly_rounded(r, storage, os_)[inner]
+        got = g.cpu()[inner]
+        naive_s = correctly_rounded(nv, storage, os_)[inner]
+        lib_wrong = float((got != want).double().mean())
+        naive_wrong = float((naive_s != want).double().mean())
+        say("%s s%s: not correctly rounded: library %.4f, naive FP32 %.4f of %d points"
+            % (B.DTYPE_NAMES[storage], name, lib_wrong, naive_wrong, want.numel()))
+        assert lib_wrong <= 0.01, "s%s: %.3f of the library's outputs are not correctly rounded" % (name, lib_wrong)
+        assert naive_wrong >= 0.05 and naive_wrong >= 5 * lib_wrong, \
+            "s%s: the fields do not separate compensated from naive FP32 (%.3f vs %.3f)" % (name, lib_wrong, naive_wrong)
