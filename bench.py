@@ -634,17 +634,16 @@ def batched_leg(dev, stream, f64_gpts, log, replays=100, tuning=None, per_domain
         per_dom_ms, gp, plans = None, None, None
         if per_domain:
             # baseline: the same timestep with one pw_advect launch per domain,
-            # also as a graph (recorded on a stream of its own)
+            # also as a graph
             plans = batch.per_domain_plans()
-            rec_stream = torch.cuda.Stream()
             torch.cuda.synchronize()
 
-            def per_domain_step():
-                batch.perturb(plan, inputs.SEED_BASE + 1, 1e-3, rec_stream)
-                batch.fill_halo(plan, rec_stream)
-                batch.advect_per_domain(plans, rec_stream)
+            def per_domain_step(rs):
+                batch.perturb(plan, inputs.SEED_BASE + 1, 1e-3, rs)
+                batch.fill_halo(plan, rs)
+                batch.advect_per_domain(plans, rs)
 
-            gp = B.Graph.record(per_domain_step, rec_stream)
+            gp = B.Graph.record(per_domain_step)
             per_dom_ms = time_steps(lambda: gp.launch(stream), 20, 3, stream)
             log("batched", name, "per-domain launches %.4f ms" % per_dom_ms)
         ebytes = metrics.ELEM_BYTES[name]

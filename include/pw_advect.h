@@ -17,12 +17,13 @@
  *   Every output is written as 0 at k = 1, and sw at k = nz (+0 for the
  *   floating storage types).
  *
- * Inputs are taken to be finite (fixed-point inputs always are).  For FP64,
- * BF16 and FP16 storage the staged kernels evaluate the column top as the
- * full form with the upper vertical flux multiplied by an exact zero, so a
+ * Inputs are taken to be finite (fixed-point inputs always are).  For BF16
+ * and FP16 storage the staged kernels evaluate the column top as the full
+ * form with the upper vertical flux multiplied by an exact zero, so a
  * non-finite w at level nz of a column or of its x (su) or y (sv) neighbour
  * makes su(nz) or sv(nz) NaN, although the truncated formula does not read
- * that value.
+ * that value.  FP64 and FP32 storage select the truncated form, so their
+ * column-top results never read values above the top.
  *
  * The paper prints only su; sv and sw follow the staggering that Listing 1's
  * indices imply and the 21 operations per field that Sec. III counts.
@@ -290,25 +291,29 @@ int32_t pw_perturb_batched(const pw_plan *plan, int32_t ndomains,
    perturbation's call counter lives in device memory and advances on every
    replay).
 
-   pw_graph_begin: start recording the work issued on `stream` (a hipStream_t,
-   not NULL: the null stream cannot be recorded) into a graph; work issued on
-   it is recorded, not run, until pw_graph_end.  Returns PW_ERR_CAPTURE if the
-   stream is already recording.  The recording is thread-local: the entry
-   points that allocate (plan creation, the autotuner, host-resident calls)
-   must not be called by this thread until pw_graph_end, since HIP rejects
-   an allocation during the recording and invalidates it.
-   pw_graph_end: stop the recording on `stream` and instantiate it; `graph`
-   (host out-pointer) receives the new graph.  PW_ERR_CAPTURE if the stream
-   is not recording; PW_ERR_HIP if HIP rejects the recording. */
+   pw_graph_begin: start a recording.  `stream` (host out-pointer) receives
+   a new hipStream_t (as void*) owned by the recording: library calls issued
+   on it until pw_graph_end are recorded, not run.  The recording is
+   thread-local: the entry points that allocate (plan creation, the
+   autotuner, host-resident calls) must not be called by this thread until
+   pw_graph_end, since HIP rejects an allocation during the recording and
+   invalidates it.
+   pw_graph_end: stop the recording on `stream` (from pw_graph_begin),
+   instantiate it and destroy the stream; `graph` (host out-pointer)
+   receives the new graph.  PW_ERR_CAPTURE if the stream is not recording;
+   PW_ERR_HIP if HIP rejects the recording.  (The library records on a
+   stream of its own because on MI355X a stream left alive after a capture
+   has been seen to keep later asynchronous copies of the process from
+   overlapping with kernels.) */
 typedef struct pw_graph pw_graph;
-int32_t pw_graph_begin(void *stream);
+int32_t pw_graph_begin(void **stream);
 int32_t pw_graph_end(void *stream, pw_graph **graph);
 
 /* Record `nsteps` repeated timesteps of a batched plan into a new graph --
    each step pw_perturb_batched (seed, d_call, amplitude), then
-   pw_fill_halo_batched, then pw_advect_batched, all on `d_args` -- on a
-   stream of its own (allocates the graph; not for use while another stream
-   of this thread records).  Arguments as for those calls; nsteps >= 1.
+   pw_fill_halo_batched, then pw_advect_batched, all on `d_args` -- through
+   pw_graph_begin / pw_graph_end (allocates the graph; not for use while
+   another recording of this thread is open).  Arguments as for those calls; nsteps >= 1.
    `graph` (host out-pointer) receives the graph. */
 int32_t pw_graph_capture_timestep(const pw_plan *plan, int32_t ndomains, const pw_domain_args *d_args,
                                   uint64_t seed, unsigned long long *d_call, double amplitude,

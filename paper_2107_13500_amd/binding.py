@@ -71,7 +71,7 @@ SIGNATURES = {
     "pw_fill_halo_batched": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p]),
     "pw_perturb_batched": (c_int32, [c_void_p, c_int32, c_void_p, c_uint64, c_void_p, c_double, c_void_p]),
     "pw_plan_error_count": (c_int32, [c_void_p, POINTER(c_ulonglong)]),
-    "pw_graph_begin": (c_int32, [c_void_p]),
+    "pw_graph_begin": (c_int32, [POINTER(c_void_p)]),
     "pw_graph_end": (c_int32, [c_void_p, POINTER(c_void_p)]),
     "pw_graph_capture_timestep": (c_int32, [c_void_p, c_int32, c_void_p, c_uint64, c_void_p, c_double, c_int32,
                                             POINTER(c_void_p)]),
@@ -319,6 +319,14 @@ def perturb_batched(plan: Plan, d_args, seed: int, d_call, amplitude: float, str
           "pw_perturb_batched")
 
 
+class RawStream:
+    """A hipStream_t handle the library owns (a recording stream), usable
+    wherever the binding takes a torch stream."""
+
+    def __init__(self, handle: int):
+        self.cuda_stream = handle
+
+
 class Graph:
     """Owning wrapper of a pw_graph (an instantiated HIP graph of library calls)."""
 
@@ -335,21 +343,23 @@ class Graph:
         return cls(h)
 
     @classmethod
-    def record(cls, fn, stream) -> "Graph":
-        """Record the library calls `fn()` issues on `stream` (pw_graph_begin / pw_graph_end)."""
-        s = stream_handle(stream)
-        check(lib().pw_graph_begin(s), "pw_graph_begin")
-        try:
-            fn()
-        except BaseException:
-            h = c_void_p()
-            lib().pw_graph_end(s, ctypes.byref(h))   # abandon the recording
-            if h.value:
-                lib().pw_graph_destroy(h)
-            raise
+    def record(cls, fn) -> "Graph":
+        """Record the library calls ``fn(stream)`` issues on the recording
+        stream it is given (pw_graph_begin / pw_graph_end; the stream belongs
+        to the recording and is destroyed with it)."""
         h = c_void_p()
-        check(lib().pw_graph_end(s, ctypes.byref(h)), "pw_graph_end")
-        return cls(h)
+        check(lib().pw_graph_begin(ctypes.byref(h)), "pw_graph_begin")
+        rs = RawStream(h.value)
+        g = c_void_p()
+        try:
+            fn(rs)
+        except BaseException:
+            lib().pw_graph_end(h, ctypes.byref(g))   # abandon the recording (frees its stream)
+            if g.value:
+                lib().pw_graph_destroy(g)
+            raise
+        check(lib().pw_graph_end(h, ctypes.byref(g)), "pw_graph_end")
+        return cls(g)
 
     def launch(self, stream=None) -> None:
         check(lib().pw_graph_launch(self.handle, stream_handle(stream)), "pw_graph_launch")

@@ -53,16 +53,21 @@ int32_t finish_capture(hipStream_t s, pw_graph** out) {
 
 extern "C" {
 
-int32_t pw_graph_begin(void* stream) {
-    if (!stream) return PW_ERR_INVALID_ARG;   // the null stream cannot be captured
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    hipError_t e = hipStreamIsCapturing(s, &cs);
+int32_t pw_graph_begin(void** stream) {
+    if (!stream) return PW_ERR_INVALID_ARG;
+    *stream = nullptr;
+    hipStream_t s = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (e != hipSuccess) return pw::report_hip(e);
-    if (cs != hipStreamCaptureStatusNone) return PW_ERR_CAPTURE;
     // thread-local mode: an allocation by this thread during the recording
     // is an error instead of a silently recorded side effect
-    return hip_status(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        return pw::report_hip(e);
+    }
+    *stream = s;
+    return PW_OK;
 }
 
 int32_t pw_graph_end(void* stream, pw_graph** graph) {
@@ -73,7 +78,18 @@ int32_t pw_graph_end(void* stream, pw_graph** graph) {
     hipError_t e = hipStreamIsCapturing(s, &cs);
     if (e != hipSuccess) return pw::report_hip(e);
     if (cs == hipStreamCaptureStatusNone) return PW_ERR_CAPTURE;
-    return finish_capture(s, graph);
+    const int32_t rc = finish_capture(s, graph);
+    // the recording stream goes away with the recording: a stream left alive
+    // after a capture has been seen to keep the asynchronous copies of
+    // other streams in the process from overlapping with kernels
+    e = hipStreamDestroy(s);
+    if (rc != PW_OK) return rc;
+    if (e != hipSuccess) {
+        pw_graph_destroy(*graph);
+        *graph = nullptr;
+        return pw::report_hip(e);
+    }
+    return PW_OK;
 }
 
 int32_t pw_graph_capture_timestep(const pw_plan* plan, int32_t ndomains, const pw_domain_args* d_args,
@@ -84,26 +100,18 @@ int32_t pw_graph_capture_timestep(const pw_plan* plan, int32_t ndomains, const p
     if (!plan || !d_args || !d_call || nsteps < 1) return PW_ERR_INVALID_ARG;
     if (ndomains != plan->ndomains) return PW_ERR_PLAN_MISMATCH;
     if (!plan->batch.d_table) return PW_ERR_UNSUPPORTED;
-    hipStream_t s = nullptr;
-    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
-    if (e != hipSuccess) return pw::report_hip(e);
-    int32_t rc = pw_graph_begin(s);
+    void* s = nullptr;
+    int32_t rc = pw_graph_begin(&s);
+    if (rc != PW_OK) return rc;
     for (int32_t step = 0; step < nsteps && rc == PW_OK; ++step) {
         rc = pw_perturb_batched(plan, ndomains, d_args, seed, d_call, amplitude, s);
         if (rc == PW_OK) rc = pw_fill_halo_batched(plan, ndomains, d_args, s);
         if (rc == PW_OK) rc = pw_advect_batched(plan, ndomains, d_args, s);
     }
-    if (rc == PW_OK) {
-        rc = pw_graph_end(s, graph);
-    } else {
-        // abandon a started recording
-        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) {
-            hipGraph_t g = nullptr;
-            if (hipStreamEndCapture(s, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
-        }
-    }
-    (void)hipStreamDestroy(s);
+    if (rc == PW_OK) return pw_graph_end(s, graph);
+    pw_graph* abandoned = nullptr;
+    (void)pw_graph_end(s, &abandoned);   // ends the recording and frees its stream
+    pw_graph_destroy(abandoned);
     return rc;
 }
 

@@ -258,10 +258,14 @@ __device__ __forceinline__ void pw_point(const Acc& A, int k, int nz, const Poin
         CT v_zp = A.template v<1, 0, 0>();
         const CT w_zp = A.template w<1, 0, 0>();
         const bool in = k < nz;
-        constexpr bool kZeroTop = MAY_TOP && AR::kExactZeroFlux;
+        // FP32 compute (the VALU-bound 16-bit kernels): zero values above the
+        // top make the upper vertical fluxes exact zeros, the column-top form
+        // at no extra cost for finite inputs.  FP64 compute (HBM-bound) takes
+        // the column-top form by a select instead, which costs it nothing
+        // measurable and keeps the top results independent of the values
+        // above the top, finite or not.
+        constexpr bool kZeroTop = MAY_TOP && AR::kExactZeroFlux && sizeof(CT) == 4;
         if constexpr (kZeroTop) {
-            // zero values above the top make the upper vertical fluxes exact
-            // zeros, which is the column-top form at no extra cost
             u_zp = in ? u_zp : CT(0);
             v_zp = in ? v_zp : CT(0);
         }

@@ -57,14 +57,14 @@ def test_graph_of_three_timesteps_matches_three_eager_steps(storage):
 
 
 def test_recorded_per_domain_launches_match_eager_launches():
-    """pw_graph_begin / pw_graph_end around one pw_advect per domain on a
-    side stream; replays on the default stream equal the eager launches."""
+    """pw_graph_begin / pw_graph_end around one pw_advect per domain on the
+    recording's own stream; replays on the default stream equal the eager
+    launches."""
     probs = problems(1300)
     ga, eb = BT.DeviceBatch(probs, B.F64, DEV), BT.DeviceBatch(probs, B.F64, DEV)
     plans_a, plans_b = ga.per_domain_plans(), eb.per_domain_plans()
-    side = torch.cuda.Stream()
     torch.cuda.synchronize()
-    g = B.Graph.record(lambda: ga.advect_per_domain(plans_a, side), side)
+    g = B.Graph.record(lambda rs: ga.advect_per_domain(plans_a, rs))
     for o in (o for bt in (ga, eb) for f in bt.fields for o in f[3:]):
         o.fill_(-9.0)                              # outputs must come from the replay (halos stay -9 in both)
     torch.cuda.synchronize()
@@ -83,12 +83,14 @@ def test_recorded_per_domain_launches_match_eager_launches():
 def test_graph_entry_points_reject_bad_arguments():
     l = B.lib()
     h = ctypes.c_void_p()
-    assert l.pw_graph_begin(None) == -1                       # the null stream cannot record
+    assert l.pw_graph_begin(None) == -1                       # no out-pointer
     side = torch.cuda.Stream()
     assert l.pw_graph_end(side.cuda_stream, ctypes.byref(h)) == -7   # not recording
-    assert l.pw_graph_begin(side.cuda_stream) == 0
-    assert l.pw_graph_begin(side.cuda_stream) == -7           # already recording
-    assert l.pw_graph_end(side.cuda_stream, ctypes.byref(h)) == 0   # an empty recording
+    assert l.pw_graph_end(None, ctypes.byref(h)) == -1
+    rs = ctypes.c_void_p()
+    assert l.pw_graph_begin(ctypes.byref(rs)) == 0 and rs.value
+    assert l.pw_graph_end(rs, None) == -1                     # no out-pointer: still recording
+    assert l.pw_graph_end(rs, ctypes.byref(h)) == 0           # an empty recording
     assert h.value
     assert l.pw_graph_launch(h, None) == 0
     torch.cuda.synchronize()

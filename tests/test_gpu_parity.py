@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import oracle
-from gpu_helpers import DEV, check_halo_untouched, compare_f64, device_domain, same_bits, say
+from gpu_helpers import DEV, F64_TOL, check_halo_untouched, compare_f64, device_domain, same_bits, say
 from paper_2107_13500_amd import binding as B
 from paper_2107_13500_amd import inputs
 
@@ -124,3 +124,32 @@ def test_repeat_is_deterministic():
     torch.cuda.synchronize()
     for a, b in zip(first, d.outputs):
         assert same_bits(a, b)
+
+
+@pytest.mark.parametrize("tuning", [{}, {"variant": B.VARIANT_DIRECT}, {"variant": B.VARIANT_MARCH, "chunk": 256, "seg": 4}],
+                         ids=["auto", "direct", "m256s4"])
+def test_f64_column_top_ignores_values_above_the_top(tuning):
+    """FP64 storage takes the truncated column-top form (Listing 1 drops the
+    upper vertical flux at k = nz) by a select: NaN in u and v at level 1 of
+    the next column (which sits just above the top in a staged window) and
+    Inf in w at level nz must not reach su(nz) or sv(nz).  Everywhere the
+    oracle (which never reads those values there) is finite the GPU must
+    match it to 1e-12; where it is not, the GPU must not be finite either."""
+    nx, ny, nz = 9, 12, 64
+    p = inputs.make_problem(nx, ny, nz, seed=4242)
+    for i, j in ((2, 3), (5, 7), (9, 12), (1, 1)):
+        p.u[i, j, 0] = np.nan         # level 1: above the top of column j - 1 in the window
+        p.v[i, j, 0] = np.nan
+        p.w[i, j, nz - 1] = np.inf    # level nz
+    say("non-finite inputs", tuning)
+    ref = oracle.advect_problem(p)
+    d, plan = _run(p, tuning)
+    for name, g_t, o in zip(("su", "sv", "sw"), d.outputs, ref):
+        g = g_t.cpu().numpy()[1:-1, 1:-1]
+        oi = o[1:-1, 1:-1]
+        fin = np.isfinite(oi)
+        assert np.array_equal(np.isfinite(g), fin), "%s: the non-finite points differ from the oracle's" % name
+        top_ok = np.isfinite(oi[:, :, nz - 1]).all() if name != "sw" else True
+        assert top_ok, "%s(nz) must not read the planted values" % name
+        den = np.max(np.abs(oi[fin]))
+        assert np.max(np.abs(g[fin] - oi[fin])) <= F64_TOL * den
