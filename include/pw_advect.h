@@ -162,7 +162,11 @@ typedef struct pw_plan_info {
 } pw_plan_info;
 
 /* Create a plan for `ndomains` domains (1 for pw_advect; the batch size for
-   pw_advect_batched) of storage type `storage`.
+   pw_advect_batched) of storage type `storage`.  The plan fixes the tiling:
+   contiguous chunks of each y-z plane with one halo column on either side
+   (the GPU form of the paper's Y chunking with a two-point overlap, Sec. III,
+   Fig. 4), each marched along x through a segment of planes (the shift
+   buffer of Sec. III, Fig. 3, as an LDS ring).
      plan      host out-pointer; receives the new plan.
      shapes    host array of ndomains shapes (copied).
      tuning    host pointer or NULL (library defaults).
@@ -175,11 +179,12 @@ typedef struct pw_plan_info {
 int32_t pw_advect_plan(pw_plan **plan, int32_t storage, const pw_shape *shapes,
                        int32_t ndomains, const pw_tuning *tuning);
 
-/* Free a plan and its device tables.  NULL is accepted.  The caller must make
+/* Free a plan of pw_advect_plan and its device tables.  NULL is accepted.  The caller must make
    sure no launch that uses the plan is still running. */
 int32_t pw_plan_destroy(pw_plan *plan);
 
-/* Describe a plan; `info` is a host out-pointer. */
+/* Describe a plan of pw_advect_plan (its resolved tiling and launch shape);
+   `info` is a host out-pointer. */
 int32_t pw_plan_get_info(const pw_plan *plan, pw_plan_info *info);
 
 /* su, sv, sw of one domain (paper Sec. II-A, Listing 1 for su; the mirror and
@@ -226,6 +231,11 @@ typedef struct pw_domain_args {
 
 /* su, sv, sw of all domains of a batched plan in one launch (a persistent
    grid, or one workgroup per tile with wg_per_cu = PW_WG_ONE_PER_TILE).
+   Definition as for pw_advect (Sec. II-A, Listing 1), applied to every
+   subdomain of a decomposed model that one device holds: the scheme runs once
+   per model timestep (Sec. II-A) over each subdomain, and where the paper
+   runs several kernels side by side to fill the device (Sec. IV), one launch
+   here spreads uneven subdomains over the whole GPU.
      plan       plan created with the batch's shapes (ndomains > 1 allowed, 1 too).
      ndomains   must equal the plan's ndomains (PW_ERR_PLAN_MISMATCH).
      d_args     device array of ndomains pw_domain_args.
@@ -267,7 +277,9 @@ int32_t pw_advect_batched_noalloc(int32_t storage, const pw_shape *shapes, int32
                                   unsigned long long *d_skipped, void *stream);
 
 /* Periodic x-y halo fill of u, v, w of every domain of a plan (asynchronous,
-   no allocation; may be recorded into a graph).  Each halo column (i, j)
+   no allocation; may be recorded into a graph).  The stencil has depth one
+   (Sec. II-A, Sec. III), so each call needs the one-point halo refreshed; this
+   is the repeated-timestep harness's refresh, not part of the stencil.  Each halo column (i, j)
    receives interior column (wrap(i), wrap(j)), wrap(0) = n, wrap(n+1) = 1, so
    corner columns are periodic too.  Arguments as for pw_advect_batched. */
 int32_t pw_fill_halo_batched(const pw_plan *plan, int32_t ndomains,
@@ -277,8 +289,9 @@ int32_t pw_fill_halo_batched(const pw_plan *plan, int32_t ndomains,
    r uniform in [-1, 1) from a counter-based hash of (seed, *d_call, domain,
    point) -- a SplitMix64 key per (seed, call, domain), then one 32-bit
    lowbias32 hash per element; then increment *d_call on the device.  Used to
-   change the fields between repeated timestep calls, also inside a replayed
-   graph.  d_call: device pointer to one 64-bit counter owned by the caller.
+   change the fields between repeated timestep calls (the scheme runs once
+   per model timestep, Sec. II-A), also inside a replayed graph; harness, not
+   part of the stencil.  d_call: device pointer to one 64-bit counter owned by the caller.
    Halos are not refreshed (call pw_fill_halo_batched after). */
 int32_t pw_perturb_batched(const pw_plan *plan, int32_t ndomains,
                            const pw_domain_args *d_args, uint64_t seed,
@@ -326,7 +339,8 @@ int32_t pw_graph_launch(const pw_graph *graph, void *stream);
 /* Free a graph (NULL accepted); no replay of it may still be running. */
 int32_t pw_graph_destroy(pw_graph *graph);
 
-/* Number of batched-domain records skipped so far because their shape did
+/* Error count of a batched plan (pw_advect_batched, its halo fill and
+   perturbation): the number of domain records skipped so far because their shape did
    not match the plan, a field pointer was NULL or (vector-aligned plans) not
    16-byte aligned.  Synchronous (copies one word from the device).  `count`
    is a host out-pointer. */
@@ -369,6 +383,9 @@ int32_t pw_advect_host(pw_stream_plan *plan,
 
 /* Launch-shape autotuner (the batched form's tile shapes: chunk, segment
    length, workgroups per CU; the single-domain variant, chunk and segment).
+   The paper fixes its Y chunk size by on-chip memory and finds the size of no
+   consequence above 8 (Sec. III); on the GPU chunk and segment length trade
+   halo re-reads against tiles to fill the device, so they are measured.
    Times each candidate tuning on the caller's buffers -- pw_advect with
    h_args[0] when ndomains == 1, pw_advect_batched with d_args otherwise --
    as the median of `reps` calls after one warm-up, and returns the fastest.
@@ -391,11 +408,13 @@ int32_t pw_autotune(int32_t storage, const pw_shape *shapes, int32_t ndomains,
                     const pw_tuning *candidates, int32_t ncandidates, int32_t reps,
                     pw_tuning *best, float *best_ms, float *all_ms);
 
-/* The built-in autotuner search space: writes up to `capacity` tunings to
+/* The built-in search space of pw_autotune: writes up to `capacity` tunings to
    `out` (host, may be NULL) and returns how many there are. */
 int32_t pw_autotune_candidates(int32_t batched, pw_tuning *out, int32_t capacity);
 
-/* Measurement utility (no part of the stencil): streaming copy src[s] ->
+/* Measurement utility (no part of the stencil; it measures the attainable
+   HBM bandwidth that replaces the paper's operations-times-clock
+   "theoretical performance", Sec. III, Table I): streaming copy src[s] ->
    dst[s] for s < nstreams (1..3) of `bytes` bytes each (a multiple of 16),
    with the stencil kernels' access width (16-byte loads, non-temporal 16-byte
    stores).  Its time gives the attainable HBM read+write bandwidth and its
@@ -405,8 +424,8 @@ int32_t pw_autotune_candidates(int32_t batched, pw_tuning *out, int32_t capacity
 int32_t pw_probe_copy(const void *const *src, void *const *dst, int32_t nstreams,
                       int64_t bytes, int32_t workgroups, void *stream);
 
-/* Measurement utility (no part of the stencil): the general form of
-   pw_probe_copy.  Reads nsrc (0..3) and writes ndst (0..3) buffers of
+/* Measurement utility (no part of the stencil; as pw_probe_copy, Sec. III,
+   Table I): the general form of pw_probe_copy.  Reads nsrc (0..3) and writes ndst (0..3) buffers of
    `bytes` bytes each (a multiple of 16), not both zero:
      nsrc > 0, ndst > 0  dst[s] = src[s mod nsrc] (a copy);
      nsrc = 0            dst[s] receives a fixed pattern (write only);
