@@ -325,6 +325,23 @@ def main():
         mixed = max(probes["copy_1x1"]["gbs"], probes["copy_3x3"]["gbs"])
         result["roofline"]["frac_of_copy_3x3"] = round(achieved / probes["copy_3x3"]["gbs"], 4)
         result["roofline"]["frac_of_best_mixed_copy"] = round(achieved / mixed, 4)
+        if info["variant"] == B.VARIANT_MARCH:
+            # the march kernel's own access pattern without LDS or arithmetic,
+            # over the stencil's own arrays (pw_probe_march overwrites su, sv,
+            # sw, so the stencil runs once more afterwards)
+            best = (0.0, None)
+            for sg in sorted({16, info["seg"]}):
+                if sg % 2 or nx % sg:
+                    continue
+                t = sorted(time_steps(lambda: B.probe_march(pool, sg, stream), 10, 3, stream) for _ in range(3))[1]
+                best = max(best, (abytes / (t * 1e-3) / 1e9, sg), key=lambda r: r[0])
+            d64.run(plan, stream)
+            torch.cuda.synchronize()
+            if best[1] is not None:
+                probes["march_pattern"] = {"gbs": round(best[0], 1),
+                                           "config": {"seg": best[1], "buffers": "the stencil's own arrays",
+                                                      "bytes": "the stencil's algorithmic bytes per call"}}
+                result["roofline"]["frac_of_march_pattern"] = round(achieved / best[0], 4)
         log("probe family", probes)
 
     # ---------------- the paper's Table I size (512 x 512 x 64), FP64 ----------------

@@ -448,6 +448,28 @@ int32_t pw_probe_copy(const void *const *src, void *const *dst, int32_t nstreams
 int32_t pw_probe_bandwidth(const void *const *src, int32_t nsrc, void *const *dst, int32_t ndst,
                            int64_t bytes, int32_t workgroups, int32_t flags, void *sink, void *stream);
 
+/* Measurement utility (no part of the stencil; as pw_probe_copy, Sec. III,
+   Table I): the march kernel's HBM access pattern for FP64 storage without
+   LDS or arithmetic, the reference for what the stencil's own data movement
+   can reach.  Each workgroup owns a chunk of 512 points of the y-z plane and
+   a segment of `seg` x planes (the march kernel's compact tile order); for
+   each of the segment's seg + 2 input planes it loads the chunk's window
+   (the chunk and nz points on either side) of u, v, w, and for each of its
+   seg output planes it stores the chunk of su, sv, sw: out(plane, vector t)
+   = in(plane, window vector t) + in(plane, window vector min(256 + t,
+   255 + nz)) in 2-double vectors.  Occupancy is capped at two workgroups
+   per CU, as in the FP64 march kernel.
+     u, v, w, su, sv, sw  device FP64 arrays laid out as for pw_advect
+                          (16-byte aligned); su, sv, sw are overwritten in
+                          their interior columns only.
+     shape      host pointer: nz even, 2..256; sy == nz; sx >= (ny+2) nz and
+                even; ny * nz a multiple of 512.
+     seg        even, >= 2, dividing nx.
+   Asynchronous on `stream`.  PW_ERR_INVALID_ARG for other shapes or
+   segments, PW_ERR_ALIGNMENT for a misaligned pointer. */
+int32_t pw_probe_march(const void *u, const void *v, const void *w, void *su, void *sv, void *sw,
+                       const pw_shape *shape, int32_t seg, void *stream);
+
 /* Human-readable name of a status code (static string). */
 const char *pw_status_string(int32_t status);
 

@@ -88,6 +88,7 @@ SIGNATURES = {
     "pw_probe_copy": (c_int32, [POINTER(c_void_p), POINTER(c_void_p), c_int32, c_int64, c_int32, c_void_p]),
     "pw_probe_bandwidth": (c_int32, [POINTER(c_void_p), c_int32, POINTER(c_void_p), c_int32, c_int64, c_int32,
                                      c_int32, c_void_p, c_void_p]),
+    "pw_probe_march": (c_int32, [c_void_p] * 6 + [POINTER(PwShape), c_int32, c_void_p]),
     "pw_status_string": (ctypes.c_char_p, [c_int32]),
     "pw_last_hip_error": (c_int32, []),
 }
@@ -396,6 +397,18 @@ def probe_bandwidth(srcs, dsts, nbytes: int, workgroups: int = 0, flags: int = 0
     check(lib().pw_probe_bandwidth(sp, len(srcs), dp, len(dsts), int(nbytes), int(workgroups), int(flags),
                                    sink.data_ptr() if sink is not None else None, stream_handle(stream)),
           "pw_probe_bandwidth")
+
+
+def probe_march(fields, seg: int, stream=None) -> None:
+    """pw_probe_march on six FP64 device tensors (u, v, w, su, sv, sw) of one
+    domain: the march kernel's access pattern without LDS or arithmetic; the
+    interior columns of su, sv, sw are overwritten."""
+    if len(fields) != 6:
+        raise ValueError("probe_march needs the six arrays u, v, w, su, sv, sw")
+    shape = shape_of(fields[0])
+    check_fields(F64, shape, fields, ())
+    check(lib().pw_probe_march(*[t.data_ptr() for t in fields], ctypes.byref(shape), int(seg),
+                               stream_handle(stream)), "pw_probe_march")
 
 
 class StreamPlan:

@@ -120,10 +120,113 @@ void launch_probe_in(const ProbeArgs& a, int32_t nout, int32_t flags, int64_t gr
     }
 }
 
+// ---------------------------------------------------------------------------
+// The march kernel's HBM access pattern for FP64 storage, without LDS or
+// arithmetic.  Each workgroup owns a chunk of 512 points of the y-z plane and
+// a segment of x planes, mapped to the XCDs in the march kernel's compact
+// order (XCD x owns the chunk range [x nc / 8, (x + 1) nc / 8) of every
+// segment, all XCDs advance through the segments together).  For each of the
+// segment's seg + 2 input planes it loads the chunk's window -- the chunk and
+// nz points on either side -- of the three inputs; for each of its seg output
+// planes it stores the chunk of the three outputs.  Two planes are in flight
+// in registers, and occupancy is capped at two workgroups per CU with
+// dynamic LDS, as the FP64 march kernel's registers cap it.  Stored value:
+// out(plane, chunk vector t) = in(plane, window vector t) + in(plane, window
+// vector min(256 + t, last)), so a test can check every access.
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+constexpr int kMarchProbeLds = 56 * 1024;
+
+struct MarchProbeArgs {
+    const f64x2* in[3];
+    f64x2* out[3];
+    int64_t sx2;    // plane stride in 2-double vectors
+    int32_t nzv;    // nz / 2
+    int32_t nx;
+    int32_t nchunks;
+    int32_t cpx;    // slots per XCD and segment
+    int32_t seg;
+};
+
+struct MarchProbeWin {
+    f64x2 a[3][2];
+};
+
+__device__ __forceinline__ void march_probe_load(MarchProbeWin& w, const MarchProbeArgs& a, int plane, int64_t wb,
+                                                 int t) {
+    const int v1 = min(256 + t, 255 + 2 * a.nzv);   // window vectors 256 .. 255 + nz; clamped duplicates beyond
+    const int64_t off = (int64_t)min(plane, a.nx + 1) * a.sx2 + wb;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        w.a[f][0] = a.in[f][off + t];
+        w.a[f][1] = a.in[f][off + v1];
+    }
+}
+
+__device__ __forceinline__ void march_probe_store(const MarchProbeWin& w, const MarchProbeArgs& a, int plane, int64_t wb,
+                                                  int t) {
+    const int64_t off = (int64_t)plane * a.sx2 + wb + a.nzv + t;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) __builtin_nontemporal_store(w.a[f][0] + w.a[f][1], a.out[f] + off);
+}
+
+__global__ __launch_bounds__(256) void pw_march_probe_kernel(MarchProbeArgs a) {
+    const int b = blockIdx.x;
+    const int x = b % 8, slot = b / 8;
+    const int sgi = slot / a.cpx;
+    const int c = x * a.nchunks / 8 + slot % a.cpx;
+    if (c >= (x + 1) * a.nchunks / 8) return;   // empty slot, whole workgroup
+    const int t = threadIdx.x;
+    const int64_t wb = (int64_t)c * 256;         // window start: chunk start - nz, in vectors
+    const int i0 = sgi * a.seg;                  // first input plane of the segment
+    MarchProbeWin w0, w1;
+    march_probe_load(w0, a, i0, wb, t);
+    march_probe_load(w1, a, i0 + 1, wb, t);
+    // seg is even: planes i0 + q (w0) and i0 + q + 1 (w1) per pass
+    for (int q = 0; q < a.seg + 2; q += 2) {
+        if (q >= 1) march_probe_store(w0, a, i0 + q, wb, t);
+        march_probe_load(w0, a, i0 + q + 2, wb, t);
+        if (q + 1 <= a.seg) march_probe_store(w1, a, i0 + q + 1, wb, t);
+        march_probe_load(w1, a, i0 + q + 3, wb, t);
+    }
+}
+
 }  // namespace
 }  // namespace pw
 
 using namespace pw;
+
+extern "C" int32_t pw_probe_march(const void* u, const void* v, const void* w, void* su, void* sv, void* sw,
+                                  const pw_shape* shape, int32_t seg, void* stream) {
+    if (!u || !v || !w || !su || !sv || !sw || !shape) return PW_ERR_INVALID_ARG;
+    const pw_shape& s = *shape;
+    if (s.reserved != 0 || s.nx < 1 || s.ny < 1 || s.nz < 2 || s.nz > 256 || s.nz % 2) return PW_ERR_INVALID_ARG;
+    if (s.sy != s.nz || s.sx < (int64_t)(s.ny + 2) * s.nz || s.sx % 2) return PW_ERR_INVALID_ARG;
+    if (((int64_t)s.ny * s.nz) % 512) return PW_ERR_INVALID_ARG;
+    if (seg < 2 || seg % 2 || s.nx % seg) return PW_ERR_INVALID_ARG;
+    const void* ins[3] = {u, v, w};
+    void* outs[3] = {su, sv, sw};
+    MarchProbeArgs a{};
+    for (int f = 0; f < 3; ++f) {
+        if (reinterpret_cast<uintptr_t>(ins[f]) % 16 || reinterpret_cast<uintptr_t>(outs[f]) % 16)
+            return PW_ERR_ALIGNMENT;
+        a.in[f] = static_cast<const f64x2*>(ins[f]);
+        a.out[f] = static_cast<f64x2*>(outs[f]);
+    }
+    a.sx2 = s.sx / 2;
+    a.nzv = s.nz / 2;
+    a.nx = s.nx;
+    a.nchunks = (int32_t)((int64_t)s.ny * s.nz / 512);
+    a.cpx = (a.nchunks + 7) / 8;
+    a.seg = seg;
+    const int64_t grid = (int64_t)8 * a.cpx * (s.nx / seg);
+    if (grid >= (int64_t(1) << 31)) return PW_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(pw_march_probe_kernel, dim3((unsigned)grid), dim3(256), kMarchProbeLds,
+                       static_cast<hipStream_t>(stream), a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return report_hip(e);
+    return PW_OK;
+}
 
 extern "C" int32_t pw_probe_bandwidth(const void* const* src, int32_t nsrc, void* const* dst, int32_t ndst,
                                       int64_t bytes, int32_t workgroups, int32_t flags, void* sink, void* stream) {
