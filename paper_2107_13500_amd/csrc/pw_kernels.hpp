@@ -118,13 +118,20 @@ __device__ __forceinline__ void store_pair(ST* p, typename compute_of<ST>::type 
         __builtin_memcpy(&bits, &h, 4);
         __builtin_nontemporal_store(bits, reinterpret_cast<uint32_t*>(p));
     } else {
-        // int16: from_compute's rounding and clamp, then one packing
-        // conversion of the two in-range integers (v_cvt_pk_i16_i32)
+        // int16, the result of from_compute in fewer instructions: clamp to
+        // the int16 range (NaN becomes -32768), then add 1.5 * 2^23.  The sum
+        // lies in [2^23, 2^24), where FP32 values are the integers, so the
+        // addition itself rounds to the nearest integer, ties to even (the
+        // offset is even); the offset is a multiple of 2^16, so the low 16
+        // bits of the sum are that integer in two's complement.  One byte
+        // permutation packs the two low halves.  (Clamping before rounding
+        // gives the same result: the bounds are integers.)
         static_assert(std::is_same<ST, fx16_t>::value, "int16 fixed point");
-        typedef short i16x2 __attribute__((ext_vector_type(2)));
-        const i16x2 h = __builtin_amdgcn_cvt_pk_i16(fx16_round(a), fx16_round(b));
-        uint32_t bits;
-        __builtin_memcpy(&bits, &h, 4);
+        constexpr float kRoundOffset = 12582912.0f;   // 1.5 * 2^23
+        const float ra = __builtin_fminf(__builtin_fmaxf(a, -32768.0f), 32767.0f) + kRoundOffset;
+        const float rb = __builtin_fminf(__builtin_fmaxf(b, -32768.0f), 32767.0f) + kRoundOffset;
+        // bytes 0, 1 of ra, then bytes 0, 1 of rb
+        const uint32_t bits = __builtin_amdgcn_perm(__float_as_uint(rb), __float_as_uint(ra), 0x05040100u);
         __builtin_nontemporal_store(bits, reinterpret_cast<uint32_t*>(p));
     }
 }
