@@ -117,12 +117,16 @@ typedef struct pw_shape {
    seg        x planes one workgroup marches through (>= 1).  In the batched
               kernel each domain splits its nx planes into n = ceil(nx / seg)
               segments of ceil(nx / n) planes (at most seg; the last may be
-              shorter), so a domain's tiles have nearly equal length.
+              shorter), so a domain's tiles have nearly equal length; the
+              batched default is 16 for 4- and 8-byte storage and 64 for the
+              16-bit types.
    block      threads per workgroup of the direct variant: 64, 128, 256 or 512.
-   wg_per_cu  resident workgroups per compute unit of the persistent batched
-              launch (1..8; further capped by LDS), or PW_WG_ONE_PER_TILE:
-              one workgroup per tile instead of a persistent grid, so the
-              hardware hands out the tiles in order (still one launch). */
+   wg_per_cu  batched launches: 0 (the default) or PW_WG_ONE_PER_TILE runs
+              one workgroup per tile, so the hardware hands out the tiles in
+              order (one launch; the tiles are taken longest first); 1..8
+              runs a persistent grid of that many resident workgroups per
+              compute unit (further capped by LDS and registers), whose
+              workgroups walk the tiles in the caller's domain order. */
 #define PW_WG_ONE_PER_TILE (-1)
 typedef struct pw_tuning {
     int32_t variant;
@@ -229,8 +233,8 @@ typedef struct pw_domain_args {
     pw_scales scales;
 } pw_domain_args;
 
-/* su, sv, sw of all domains of a batched plan in one launch (a persistent
-   grid, or one workgroup per tile with wg_per_cu = PW_WG_ONE_PER_TILE).
+/* su, sv, sw of all domains of a batched plan in one launch (one workgroup
+   per tile by default, or a persistent grid with wg_per_cu 1..8).
    Definition as for pw_advect (Sec. II-A, Listing 1), applied to every
    subdomain of a decomposed model that one device holds: the scheme runs once
    per model timestep (Sec. II-A) over each subdomain, and where the paper

@@ -24,7 +24,7 @@ std::vector<pw_tuning> default_candidates(bool batched) {
     for (int ch : chunks)
         for (int sg : segs) {
             if (batched) {
-                for (int wpc : {0, 2, 4, PW_WG_ONE_PER_TILE}) c.push_back(pw_tuning{PW_VARIANT_MARCH, ch, sg, 0, wpc});
+                for (int wpc : {8, 2, 4, PW_WG_ONE_PER_TILE}) c.push_back(pw_tuning{PW_VARIANT_MARCH, ch, sg, 0, wpc});
             } else {
                 c.push_back(pw_tuning{PW_VARIANT_MARCH, ch, sg, 0, 0});
             }
