@@ -205,6 +205,24 @@ __global__ __launch_bounds__(NT) void pw_batched_kernel(const BatchDomain* __res
     }
 }
 
+// Storage elements moved as raw bits through global pointers (the storage
+// structs cannot be assigned through an address-space-qualified lvalue).
+template <int N> struct bits_of;
+template <> struct bits_of<2> { using type = uint16_t; };
+template <> struct bits_of<4> { using type = uint32_t; };
+template <> struct bits_of<8> { using type = uint64_t; };
+template <typename ST> using storage_bits = typename bits_of<sizeof(ST)>::type;
+template <typename ST> __device__ __forceinline__ ST from_bits(storage_bits<ST> u) {
+    ST x;
+    __builtin_memcpy(&x, &u, sizeof(ST));
+    return x;
+}
+template <typename ST> __device__ __forceinline__ storage_bits<ST> to_bits(ST x) {
+    storage_bits<ST> u;
+    __builtin_memcpy(&u, &x, sizeof(ST));
+    return u;
+}
+
 // Periodic x-y halo of u, v, w.  Each halo column (i, j) copies interior
 // column (wrap(i), wrap(j)) with wrap(0) = n, wrap(n + 1) = 1 -- the same
 // result as filling x faces first and then y faces over the halo'd x range.
@@ -238,7 +256,8 @@ __global__ __launch_bounds__(256) void pw_halo_kernel(const BatchDomain* __restr
     const int sj = j == 0 ? b.ny : (j == b.ny + 1 ? 1 : j);
     const int64_t dst = k + (int64_t)j * b.sy + (int64_t)i * b.sx;
     const int64_t src = k + (int64_t)sj * b.sy + (int64_t)si * b.sx;
-    ST* f[3] = {(ST*)a.u, (ST*)a.v, (ST*)a.w};
+    using U = storage_bits<ST>;
+    global_ptr<U> f[3] = {as_global((U*)a.u), as_global((U*)a.v), as_global((U*)a.w)};
 #pragma unroll
     for (int q = 0; q < 3; ++q) f[q][dst] = f[q][src];
 }
@@ -266,37 +285,71 @@ __device__ __forceinline__ uint32_t lowbias32(uint32_t x) {
 // counter-based hash of (seed, call, domain, field, point); `call` is read
 // from device memory so a captured graph perturbs differently on each replay.
 // The (seed, call, domain) key is mixed once by SplitMix64; each element then
-// costs one 32-bit hash.
+// costs one 32-bit hash of its field and its point index g = k + nz ((j - 1) +
+// ny (i - 1)), so the values do not depend on how the work is split.
+// One workgroup per tile of the plan (the batched kernel's split: a chunk of
+// the (j, k) points of a plane times a segment of x planes), so every
+// workgroup of the grid has work whatever the spread of domain sizes; each
+// thread reads the points of kPerturbPlanes planes before it writes them.
+constexpr int kPerturbPlanes = 4;
+
 template <typename ST>
-__global__ __launch_bounds__(256) void pw_perturb_kernel(const BatchDomain* __restrict__ table,
+__global__ __launch_bounds__(256) void pw_perturb_kernel(const BatchDomain* __restrict__ table, int ndom, int chunk,
                                                          const pw_domain_args* __restrict__ args, uint64_t seed,
                                                          const unsigned long long* __restrict__ call, double amp) {
     using CT = typename compute_of<ST>::type;
-    const BatchDomain b = table[blockIdx.y];
+    const int64_t t = blockIdx.x;
+    const BatchDomain b = table[find_domain(table, ndom, t)];
     const int dom = b.rec;   // the caller's domain index keys the hash
     const pw_domain_args& a = args[dom];
     if (!shape_matches(a.shape, b)) return;
-    const uint32_t g = blockIdx.x * 256u + threadIdx.x;
-    const uint32_t npts = (uint32_t)b.nx * (uint32_t)b.ny * (uint32_t)b.nz;   // < 2^31 (checked at plan time)
-    if (g >= npts) return;
-    const uint32_t nz = (uint32_t)b.nz, ny = (uint32_t)b.ny;
-    const uint32_t k = g % nz;
-    const uint32_t col = g / nz;
-    const uint32_t j = col % ny + 1;
-    const uint32_t i = col / ny + 1;
-    const int64_t o = k + (int64_t)j * b.sy + (int64_t)i * b.sx;
+    const int64_t local = t - b.tile_begin;
+    const int c = (int)(local % b.nchunks);
+    const int sg = (int)(local / b.nchunks);
+    const int i0 = 1 + sg * b.seg;                 // <= nx: segments start at or before plane nx
+    const int i1 = min(i0 + b.seg - 1, b.nx);
+    const uint32_t nz = (uint32_t)b.nz, nyz = (uint32_t)b.ny * (uint32_t)b.nz;   // nx ny nz < 2^31 (plan time)
+    const uint32_t pend = min((uint32_t)(c + 1) * (uint32_t)chunk, nyz);
     const uint64_t key64 = splitmix64(seed ^ splitmix64((uint64_t)(*call) * 0x100000001b3ull + (uint64_t)dom));
     const uint32_t key = (uint32_t)key64 ^ (uint32_t)(key64 >> 32);
-    ST* f[2] = {(ST*)a.u, (ST*)a.v};
-    const float sc[2] = {scaled_type<ST>::value ? scale_or_one(a.scales.in_scale[0]) : 1.0f,
-                         scaled_type<ST>::value ? scale_or_one(a.scales.in_scale[1]) : 1.0f};
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    using U = storage_bits<ST>;
+    global_ptr<U> f[2] = {as_global((U*)a.u), as_global((U*)a.v)};
+    const CT sc[2] = {static_cast<CT>(scaled_type<ST>::value ? scale_or_one(a.scales.in_scale[0]) : 1.0f),
+                      static_cast<CT>(scaled_type<ST>::value ? scale_or_one(a.scales.in_scale[1]) : 1.0f)};
+    uint32_t p = 0;
+    // x + amp r (times the field's scale) at plane i of point p, field q
+    auto perturbed = [&](CT x, int i, int q) {
+        const uint32_t g = (uint32_t)(i - 1) * nyz + p;
         const uint32_t h = lowbias32(key ^ lowbias32(2u * g + (uint32_t)q));
         const float r = (float)(h >> 8) * 0x1.0p-23f - 1.0f;   // [-1, 1)
-        CT x = to_compute(f[q][o]);
-        x += static_cast<CT>(amp * (double)r) * static_cast<CT>(sc[q]);
-        f[q][o] = from_compute<ST>(x);
+        return x + static_cast<CT>(amp * (double)r) * sc[q];
+    };
+    for (p = (uint32_t)c * (uint32_t)chunk + threadIdx.x; p < pend; p += 256) {
+        const uint32_t k = p % nz;
+        const uint32_t j = p / nz + 1;
+        const int64_t col = k + (int64_t)j * b.sy;
+        // full groups of kPerturbPlanes planes without conditions (so the
+        // compiler keeps all their loads in flight), then the rest one by one
+        int i = i0;
+        for (; i + kPerturbPlanes - 1 <= i1; i += kPerturbPlanes) {
+            CT x[kPerturbPlanes][2];
+#pragma unroll
+            for (int u = 0; u < kPerturbPlanes; ++u)
+#pragma unroll
+                for (int q = 0; q < 2; ++q) x[u][q] = to_compute(from_bits<ST>(f[q][col + (int64_t)(i + u) * b.sx]));
+#pragma unroll
+            for (int u = 0; u < kPerturbPlanes; ++u)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    f[q][col + (int64_t)(i + u) * b.sx] = to_bits(from_compute<ST>(perturbed(x[u][q], i + u, q)));
+        }
+        for (; i <= i1; ++i) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const CT x = to_compute(from_bits<ST>(f[q][col + (int64_t)i * b.sx]));
+                f[q][col + (int64_t)i * b.sx] = to_bits(from_compute<ST>(perturbed(x, i, q)));
+            }
+        }
     }
 }
 
@@ -411,12 +464,6 @@ hipError_t dispatch_batched(int32_t storage, int32_t chunk, int32_t kind, const 
 int64_t max_halo_elems(const pw_plan* p) {
     int64_t m = 0;
     for (const pw_shape& s : p->shapes) m = std::max<int64_t>(m, (int64_t)(2 * (s.nx + 2) + 2 * s.ny) * s.nz);
-    return m;
-}
-
-int64_t max_points(const pw_plan* p) {
-    int64_t m = 0;
-    for (const pw_shape& s : p->shapes) m = std::max<int64_t>(m, (int64_t)s.nx * s.ny * s.nz);
     return m;
 }
 
@@ -628,28 +675,30 @@ int32_t pw_perturb_batched(const pw_plan* plan, int32_t ndomains, const pw_domai
     if (!plan || !d_args || !d_call || !std::isfinite(amplitude)) return PW_ERR_INVALID_ARG;
     if (ndomains != plan->ndomains) return PW_ERR_PLAN_MISMATCH;
     if (!plan->batch.d_table) return PW_ERR_UNSUPPORTED;
-    const int64_t blocks = (max_points(plan) + 255) / 256;
-    dim3 grid((unsigned)blocks, (unsigned)ndomains);
+    const Launch& L = plan->batch.launch;
+    if (L.tiles >= (int64_t(1) << 31)) return PW_ERR_UNSUPPORTED;
+    const dim3 grid((unsigned)L.tiles);   // one workgroup per tile
     hipStream_t s = static_cast<hipStream_t>(stream);
     const BatchDomain* tb = plan->batch.d_table;
+    const int nd = plan->ndomains, ch = L.chunk;
     switch (plan->storage) {
         case PW_F64:
-            hipLaunchKernelGGL(pw_perturb_kernel<double>, grid, dim3(256), 0, s, tb, d_args, seed, d_call, amplitude);
+            hipLaunchKernelGGL(pw_perturb_kernel<double>, grid, dim3(256), 0, s, tb, nd, ch, d_args, seed, d_call, amplitude);
             break;
         case PW_F32:
-            hipLaunchKernelGGL(pw_perturb_kernel<float>, grid, dim3(256), 0, s, tb, d_args, seed, d_call, amplitude);
+            hipLaunchKernelGGL(pw_perturb_kernel<float>, grid, dim3(256), 0, s, tb, nd, ch, d_args, seed, d_call, amplitude);
             break;
         case PW_BF16:
-            hipLaunchKernelGGL(pw_perturb_kernel<bf16_t>, grid, dim3(256), 0, s, tb, d_args, seed, d_call, amplitude);
+            hipLaunchKernelGGL(pw_perturb_kernel<bf16_t>, grid, dim3(256), 0, s, tb, nd, ch, d_args, seed, d_call, amplitude);
             break;
         case PW_F16:
-            hipLaunchKernelGGL(pw_perturb_kernel<f16_t>, grid, dim3(256), 0, s, tb, d_args, seed, d_call, amplitude);
+            hipLaunchKernelGGL(pw_perturb_kernel<f16_t>, grid, dim3(256), 0, s, tb, nd, ch, d_args, seed, d_call, amplitude);
             break;
         case PW_I16:
-            hipLaunchKernelGGL(pw_perturb_kernel<fx16_t>, grid, dim3(256), 0, s, tb, d_args, seed, d_call, amplitude);
+            hipLaunchKernelGGL(pw_perturb_kernel<fx16_t>, grid, dim3(256), 0, s, tb, nd, ch, d_args, seed, d_call, amplitude);
             break;
         case PW_I32:
-            hipLaunchKernelGGL(pw_perturb_kernel<fx32_t>, grid, dim3(256), 0, s, tb, d_args, seed, d_call, amplitude);
+            hipLaunchKernelGGL(pw_perturb_kernel<fx32_t>, grid, dim3(256), 0, s, tb, nd, ch, d_args, seed, d_call, amplitude);
             break;
         default: return PW_ERR_UNSUPPORTED;
     }

@@ -81,15 +81,40 @@ __host__ __device__ inline void fold_coefficients(double tcx, double tcy, const 
     }
 }
 
+// One load of a Raw value (2, 4, 8 or 16 bytes) through a global pointer, as
+// a plain integer vector (HIP's vector structs cannot be assigned from an
+// address-space-qualified lvalue), copied bit for bit.
+template <typename Raw>
+__device__ __forceinline__ Raw load_global(global_ptr<const char> p) {
+    typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
+    typedef uint32_t u32x2v __attribute__((ext_vector_type(2)));
+    Raw r;
+    if constexpr (sizeof(Raw) == 16) {
+        const u32x4v x = *reinterpret_cast<global_ptr<const u32x4v>>(p);
+        __builtin_memcpy(&r, &x, 16);
+    } else if constexpr (sizeof(Raw) == 8) {
+        const u32x2v x = *reinterpret_cast<global_ptr<const u32x2v>>(p);
+        __builtin_memcpy(&r, &x, 8);
+    } else if constexpr (sizeof(Raw) == 4) {
+        const uint32_t x = *reinterpret_cast<global_ptr<const uint32_t>>(p);
+        __builtin_memcpy(&r, &x, 4);
+    } else {
+        static_assert(sizeof(Raw) == 2, "2, 4, 8 or 16 bytes");
+        const uint16_t x = *reinterpret_cast<global_ptr<const uint16_t>>(p);
+        __builtin_memcpy(&r, &x, 2);
+    }
+    return r;
+}
+
 template <typename ST>
-__device__ __forceinline__ void store_out(ST* p, typename compute_of<ST>::type x) {
+__device__ __forceinline__ void store_out(global_ptr<ST> p, typename compute_of<ST>::type x) {
     ST y = from_compute<ST>(x);
     if constexpr (sizeof(ST) == 2) {
         uint16_t bits;
         __builtin_memcpy(&bits, &y, 2);
-        __builtin_nontemporal_store(bits, reinterpret_cast<uint16_t*>(p));
+        __builtin_nontemporal_store(bits, reinterpret_cast<global_ptr<uint16_t>>(p));
     } else if constexpr (std::is_same<ST, fx32_t>::value) {
-        __builtin_nontemporal_store(y.v, reinterpret_cast<int32_t*>(p));
+        __builtin_nontemporal_store(y.v, reinterpret_cast<global_ptr<int32_t>>(p));
     } else {
         __builtin_nontemporal_store(y, p);
     }
@@ -103,20 +128,20 @@ typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 template <typename ST>
-__device__ __forceinline__ void store_pair(ST* p, typename compute_of<ST>::type a, typename compute_of<ST>::type b) {
+__device__ __forceinline__ void store_pair(global_ptr<ST> p, typename compute_of<ST>::type a, typename compute_of<ST>::type b) {
     if constexpr (std::is_same<ST, double>::value) {
-        __builtin_nontemporal_store(f64x2{a, b}, reinterpret_cast<f64x2*>(p));
+        __builtin_nontemporal_store(f64x2{a, b}, reinterpret_cast<global_ptr<f64x2>>(p));
     } else if constexpr (std::is_same<ST, float>::value) {
-        __builtin_nontemporal_store(f32x2{a, b}, reinterpret_cast<f32x2*>(p));
+        __builtin_nontemporal_store(f32x2{a, b}, reinterpret_cast<global_ptr<f32x2>>(p));
     } else if constexpr (std::is_same<ST, fx32_t>::value) {
         typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
-        __builtin_nontemporal_store(i32x2{from_compute<ST>(a).v, from_compute<ST>(b).v}, reinterpret_cast<i32x2*>(p));
+        __builtin_nontemporal_store(i32x2{from_compute<ST>(a).v, from_compute<ST>(b).v}, reinterpret_cast<global_ptr<i32x2>>(p));
     } else if constexpr (std::is_same<ST, bf16_t>::value || std::is_same<ST, f16_t>::value) {
         using H2 = typename std::conditional<std::is_same<ST, bf16_t>::value, bf16x2, f16x2>::type;
         const H2 h = __builtin_convertvector(f32x2{a, b}, H2);
         uint32_t bits;
         __builtin_memcpy(&bits, &h, 4);
-        __builtin_nontemporal_store(bits, reinterpret_cast<uint32_t*>(p));
+        __builtin_nontemporal_store(bits, reinterpret_cast<global_ptr<uint32_t>>(p));
     } else {
         // int16, the result of from_compute in fewer instructions: clamp to
         // the int16 range (NaN becomes -32768), then add 1.5 * 2^23.  The sum
@@ -132,7 +157,7 @@ __device__ __forceinline__ void store_pair(ST* p, typename compute_of<ST>::type 
         const float rb = __builtin_fminf(__builtin_fmaxf(b, -32768.0f), 32767.0f) + kRoundOffset;
         // bytes 0, 1 of ra, then bytes 0, 1 of rb
         const uint32_t bits = __builtin_amdgcn_perm(__float_as_uint(rb), __float_as_uint(ra), 0x05040100u);
-        __builtin_nontemporal_store(bits, reinterpret_cast<uint32_t*>(p));
+        __builtin_nontemporal_store(bits, reinterpret_cast<global_ptr<uint32_t>>(p));
     }
 }
 
@@ -148,11 +173,11 @@ __device__ __forceinline__ PointCoefs<typename compute_of<ST>::type> point_coefs
     c.yw = static_cast<CT>(d.cy[2]);
     double z1 = 0.0, z2 = 0.0, e1 = 0.0, e2 = 0.0;
     if (k >= 2) {
-        z1 = d.tzc1[k - 1];
-        z2 = d.tzc2[k - 1];
+        z1 = as_global(d.tzc1)[k - 1];
+        z2 = as_global(d.tzc2)[k - 1];
         if (k < d.nz) {
-            e1 = d.tzd1[k - 1];
-            e2 = d.tzd2[k - 1];
+            e1 = as_global(d.tzd1)[k - 1];
+            e2 = as_global(d.tzd2)[k - 1];
         }
     }
     c.z1u = static_cast<CT>(z1 * d.cz[0]);
@@ -197,9 +222,9 @@ __global__ __launch_bounds__(NT) void pw_direct_kernel(DomainArgs d) {
     const PointCoefs<CT> c = point_coefs<ST>(d, k);
     CT su, sv, sw;
     pw_point<typename arith_of<ST>::type, true>(A, k, d.nz, c, su, sv, sw);
-    store_out(static_cast<ST*>(d.su) + off, su);
-    store_out(static_cast<ST*>(d.sv) + off, sv);
-    store_out(static_cast<ST*>(d.sw) + off, sw);
+    store_out(as_global(static_cast<ST*>(d.su) + off), su);
+    store_out(as_global(static_cast<ST*>(d.sv) + off), sv);
+    store_out(as_global(static_cast<ST*>(d.sw) + off), sw);
 }
 
 // ---------------------------------------------------------------------------
@@ -405,7 +430,7 @@ struct MarchTile {
     // offset loff[r].  Planes are loaded in order, so each load advances gp
     // by one plane (a 64-bit add of a uniform stride instead of a multiply).
     int fsel[NVR];
-    const char* gp[NVR];
+    global_ptr<const char> gp[NVR];
     int loff[NVR];
     // DIST planes in flight: plane p lives in register set (p - i_begin + 1) % DIST
     static_assert(DIST == 2 || DIST == 3, "two or three planes in flight");
@@ -437,7 +462,7 @@ struct MarchTile {
             const int q = (v - (f < 0 ? 0 : f) * nvec) * VW;
             fsel[r] = f;
             const ST* base = static_cast<const ST*>(f == 0 ? d.u : (f == 1 ? d.v : d.w));
-            gp[r] = reinterpret_cast<const char*>(base + (wb + q));   // plane 0
+            gp[r] = as_global(reinterpret_cast<const char*>(base + (wb + q)));   // plane 0
             loff[r] = (f < 0 ? 0 : f) * wpad() + q;
         }
 #pragma unroll
@@ -498,7 +523,7 @@ struct MarchTile {
         const int64_t ps = d.sx * (int64_t)sizeof(ST);   // uniform plane stride in bytes
 #pragma unroll
         for (int r = 0; r < NVR; ++r) {
-            if (EXACT || fsel[r] >= 0) dst[r] = *reinterpret_cast<const Raw*>(gp[r]);
+            if (EXACT || fsel[r] >= 0) dst[r] = load_global<Raw>(gp[r]);
             gp[r] += ps;
         }
     }
@@ -664,7 +689,8 @@ struct MarchTile {
                 pw_point<AR, false>(A, kk[q], nz(), c, res[q][0], res[q][1], res[q][2]);
             }
         }
-        ST* outs[3] = {static_cast<ST*>(d.su) + obase, static_cast<ST*>(d.sv) + obase, static_cast<ST*>(d.sw) + obase};
+        global_ptr<ST> outs[3] = {as_global(static_cast<ST*>(d.su) + obase), as_global(static_cast<ST*>(d.sv) + obase),
+                                  as_global(static_cast<ST*>(d.sw) + obase)};
         if constexpr (PAIR) {
 #pragma unroll
             for (int q = 0; q < PPT; q += 2) {

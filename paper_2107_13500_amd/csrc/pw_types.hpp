@@ -19,6 +19,15 @@ struct fx32_t {
     int32_t v;
 };
 
+// Device memory seen through the global address space.  Loads and stores
+// through such a pointer are global_* instructions, which count against
+// vmcnt only.  Through a generic pointer that the compiler cannot prove
+// global -- one read from device memory, as a batched record's fields are --
+// they are flat_* instructions, which also count against lgkmcnt, so every
+// wait for an LDS read would also wait for all memory loads in flight.
+template <typename T> using global_ptr = __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ global_ptr<T> as_global(T* p) { return (global_ptr<T>)p; }
+
 // ---------------------------------------------------------------------------
 // compute type of each storage type
 // ---------------------------------------------------------------------------

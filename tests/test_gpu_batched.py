@@ -215,6 +215,60 @@ def test_perturb_is_deterministic_and_interior_only():
     assert not torch.equal(d1, d2)
 
 
+M64 = (1 << 64) - 1
+
+
+def splitmix64(x: int) -> int:
+    """SplitMix64 finaliser (Steele, Lea and Flood, OOPSLA 2014), on Python ints."""
+    x = (x + 0x9E3779B97F4A7C15) & M64
+    x = ((x ^ (x >> 30)) * 0xBF58476D1CE4E5B9) & M64
+    x = ((x ^ (x >> 27)) * 0x94D049BB133111EB) & M64
+    return x ^ (x >> 31)
+
+
+def lowbias32(x):
+    """lowbias32 (C. Wellons, 2018) on a numpy uint32 array."""
+    x = x ^ (x >> np.uint32(16))
+    x = x * np.uint32(0x7FEB352D)
+    x = x ^ (x >> np.uint32(15))
+    x = x * np.uint32(0x846CA68B)
+    return x ^ (x >> np.uint32(16))
+
+
+def expected_noise(seed, call, dom, nx, ny, nz, q):
+    """The documented perturbation r in [-1, 1) of field q (0: u, 1: v) at every
+    interior point, shape (nx, ny, nz): key = SplitMix64 of (seed, call,
+    domain), then lowbias32(key ^ lowbias32(2 g + q)) with g = k + nz ((j-1) +
+    ny (i-1)), its top 24 bits scaled to [0, 2) in FP32, minus 1."""
+    k64 = splitmix64(seed ^ splitmix64((call * 0x100000001B3 + dom) & M64))
+    key = np.uint32((k64 ^ (k64 >> 32)) & 0xFFFFFFFF)
+    g = np.arange(nx * ny * nz, dtype=np.uint32).reshape(nx, ny, nz)
+    with np.errstate(over="ignore"):
+        h = lowbias32(key ^ lowbias32(np.uint32(2) * g + np.uint32(q)))
+    return ((h >> np.uint32(8)).astype(np.float32) * np.float32(2.0 ** -23) - np.float32(1.0)).astype(np.float64)
+
+
+@pytest.mark.parametrize("tuning", [{"chunk": 256, "seg": 3}, {"chunk": 1024, "seg": 64}, None],
+                         ids=["c256s3", "c1024s64", "default"])
+def test_perturb_adds_the_documented_noise_at_every_interior_point(tuning):
+    """Every interior point of u and v moves by exactly amp * r of the
+    counter-based hash, whatever the plan's tiling, on two calls in a row."""
+    probs = small_problems(SMALL[:6], seed=710)
+    bt = BT.DeviceBatch(probs, B.F64, DEV)
+    plan = bt.plan(tuning)
+    amp = 1e-3
+    for call in range(2):
+        before = [[t.cpu().numpy().copy() for t in bt.fields[d][:2]] for d in range(len(probs))]
+        bt.perturb(plan, 99, amp)
+        torch.cuda.synchronize()
+        for d, p in enumerate(probs):
+            for q in range(2):
+                got = bt.fields[d][q].cpu().numpy()
+                want = before[d][q].copy()
+                want[1:-1, 1:-1] = before[d][q][1:-1, 1:-1] + amp * expected_noise(99, call, d, p.nx, p.ny, p.nz, q)
+                assert np.array_equal(got.view(np.int64), want.view(np.int64)), (tuning, call, d, q)
+
+
 def test_graph_replays_match_eager_steps():
     probs = small_problems(seed=800)
     ga = BT.DeviceBatch(probs, B.F64, DEV)
