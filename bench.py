@@ -166,6 +166,22 @@ def probe_family(gbytes, dev, stream, steps=10, warmup=3):
     return {m: {"gbs": round(g, 1), "config": c} for m, (g, c) in best.items()}
 
 
+def march_pattern(fields, nx, plan_seg, abytes, stream, steps=10):
+    """The march kernel's own access pattern without LDS or arithmetic
+    (pw_probe_march over the stencil's own six arrays; it overwrites su, sv,
+    sw), the best of 16-plane and the plan's segments, each the median of
+    three timings; rated in the stencil's algorithmic bytes.  Returns
+    (GB/s, segment) or (0.0, None) if no segment applies."""
+    from paper_2107_13500_amd import binding as B
+    best = (0.0, None)
+    for sg in sorted({16, plan_seg}):
+        if sg % 2 or nx % sg:
+            continue
+        t = sorted(time_steps(lambda: B.probe_march(fields, sg, stream), steps, 3, stream) for _ in range(3))[1]
+        best = max(best, (abytes / (t * 1e-3) / 1e9, sg), key=lambda r: r[0])
+    return best
+
+
 def measured_traffic(kernel_key, chunk, seg):
     """Calibrated HBM bytes per launch from the committed rocprofv3 counter summary,
     or None if the kernel sources or launch shape changed since it was taken."""
@@ -329,12 +345,7 @@ def main():
             # the march kernel's own access pattern without LDS or arithmetic,
             # over the stencil's own arrays (pw_probe_march overwrites su, sv,
             # sw, so the stencil runs once more afterwards)
-            best = (0.0, None)
-            for sg in sorted({16, info["seg"]}):
-                if sg % 2 or nx % sg:
-                    continue
-                t = sorted(time_steps(lambda: B.probe_march(pool, sg, stream), 10, 3, stream) for _ in range(3))[1]
-                best = max(best, (abytes / (t * 1e-3) / 1e9, sg), key=lambda r: r[0])
+            best = march_pattern(pool, nx, info["seg"], abytes, stream)
             d64.run(plan, stream)
             torch.cuda.synchronize()
             if best[1] is not None:
@@ -347,7 +358,8 @@ def main():
     # ---------------- the paper's Table I size (512 x 512 x 64), FP64 ----------------
     small = None
     if args.workload != "pw512" and not args.skip_pw512:
-        small = small_workload_leg("pw512", tuning, dev, stream, args.steps, args.warmup, log)
+        small = small_workload_leg("pw512", tuning, dev, stream, args.steps, args.warmup, log,
+                                   probes=not args.skip_probes)
         result["pw512"] = small["record"]
 
     # ---------------- storage-precision variants (outputs kept for the error check) ----------------
@@ -457,7 +469,7 @@ def parity_gate(result):
     return fails
 
 
-def small_workload_leg(name, tuning, dev, stream, steps, warmup, log):
+def small_workload_leg(name, tuning, dev, stream, steps, warmup, log, probes=True):
     """One more FP64 workload (inputs resident in HBM, six arrays packed in one
     allocation), timed like the headline with its own roofline; its outputs are
     kept for the parity check against the oracle."""
@@ -490,6 +502,15 @@ def small_workload_leg(name, tuning, dev, stream, steps, warmup, log):
     if info["variant"] == B.VARIANT_MARCH:
         t = measured_traffic("pw_march_f64_%s" % name, info["chunk"], info["seg"])
         rec["roofline"]["traffic"] = None if t is None else int(round(t))
+        if probes:
+            # the same access pattern without LDS or arithmetic on these arrays
+            # (overwrites su, sv, sw, so the stencil runs once more after it)
+            gbs, sg = march_pattern(pool, p.nx, info["seg"], abytes, stream, steps=max(steps, 50))
+            d.run(plan, stream)
+            torch.cuda.synchronize()
+            if sg is not None:
+                rec["roofline"]["march_pattern"] = {"gbs": round(gbs, 1), "seg": sg}
+                rec["roofline"]["frac_of_march_pattern"] = round(achieved / gbs, 4)
     log(name, rec)
     return {"record": rec, "problem": p, "domain": d, "plan": plan}
 
