@@ -1,12 +1,14 @@
-// Batched PW advection: many uneven subdomains in one persistent launch, plus
-// the periodic halo fill and the field perturbation used between repeated
+// Batched PW advection: many uneven subdomains in one launch, plus the
+// periodic halo fill and the field perturbation used between repeated
 // timestep calls.
 //
 // The plan flattens every domain's (chunk, segment) tiles into one global
-// tile range (prefix sums in a device table).  A persistent grid sized to the
-// GPU walks that range (each XCD a contiguous share); each workgroup maps a
-// tile to its domain (a binary search, then a forward scan) and runs the
-// per-tile code of the single-domain march kernel.  The per-point arithmetic
+// tile range (prefix sums in a device table).  By default one workgroup runs
+// each tile (longest tiles first, handed to the XCDs in runs of neighbouring
+// tiles); on request a persistent grid sized to the GPU walks the range
+// instead (each XCD a contiguous share).  Each workgroup maps a tile to its
+// domain (a binary search, then a forward scan) and runs the per-tile code
+// of the single-domain march kernel.  The per-point arithmetic
 // is the same source, and the library is built with FMA formed only within
 // a source expression, so each domain's result is bit-identical to a
 // pw_advect call (the result of a point does not depend on the tiling).

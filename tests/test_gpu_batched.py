@@ -322,12 +322,14 @@ def test_autotune_single_domain_default_space():
 
 
 @pytest.mark.parametrize("storage,tuning", [
-    (B.F64, None), (B.F64, {"chunk": 512, "seg": 8, "wg_per_cu": B.WG_ONE_PER_TILE}),
+    (B.F64, None), (B.F64, {"chunk": 512, "seg": 16, "wg_per_cu": 8}),
+    (B.F64, {"chunk": 512, "seg": 8, "wg_per_cu": B.WG_ONE_PER_TILE}),
     (B.F32, {"chunk": 512, "seg": 16, "wg_per_cu": B.WG_ONE_PER_TILE})],
-    ids=["f64-persistent-default", "f64-one-per-tile-c512s8", "f32-one-per-tile-c512s16"])
+    ids=["f64-default", "f64-persistent", "f64-one-per-tile-c512s8", "f32-one-per-tile-c512s16"])
 def test_full_384_domain_batch_graph(storage, tuning):
-    """The 384-subdomain configuration, with the default persistent grid and
-    with the launches the autotuner picks on MI355X (one workgroup per tile):
+    """The 384-subdomain configuration with the default launch (one workgroup
+    per tile), a persistent grid at full occupancy, and the launches the
+    autotuner picks on MI355X:
     graph-captured timestep replayed, sampled domains vs the oracle on the
     stored fields (FP64: 1e-12; FP32 storage: FP32 roundoff of the outputs
     plus its compensated arithmetic, 2^-24 + 2e-6)."""
