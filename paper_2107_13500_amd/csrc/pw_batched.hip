@@ -228,7 +228,9 @@ template <typename ST> __device__ __forceinline__ storage_bits<ST> to_bits(ST x)
 // Periodic x-y halo of u, v, w.  Each halo column (i, j) copies interior
 // column (wrap(i), wrap(j)) with wrap(0) = n, wrap(n + 1) = 1 -- the same
 // result as filling x faces first and then y faces over the halo'd x range.
-// grid: x over halo elements of the largest domain, y over domains.
+// grid: y over domains, x a number of workgroups sized to the mean domain's
+// halo; each workgroup strides over its domain's halo elements (every
+// element is written once, from an interior source, so the order is free).
 template <typename ST>
 __global__ __launch_bounds__(256) void pw_halo_kernel(const BatchDomain* __restrict__ table,
                                                       const pw_domain_args* __restrict__ args) {
@@ -236,32 +238,33 @@ __global__ __launch_bounds__(256) void pw_halo_kernel(const BatchDomain* __restr
     const pw_domain_args& a = args[b.rec];
     if (!shape_matches(a.shape, b)) return;
     const int nhalo = 2 * (b.nx + 2) + 2 * b.ny;
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (g >= (int64_t)nhalo * b.nz) return;
-    const int k = (int)(g % b.nz);
-    const int h = (int)(g / b.nz);
-    int i, j;
-    if (h < b.nx + 2) {
-        i = h;
-        j = 0;
-    } else if (h < 2 * (b.nx + 2)) {
-        i = h - (b.nx + 2);
-        j = b.ny + 1;
-    } else if (h < 2 * (b.nx + 2) + b.ny) {
-        i = 0;
-        j = 1 + h - 2 * (b.nx + 2);
-    } else {
-        i = b.nx + 1;
-        j = 1 + h - 2 * (b.nx + 2) - b.ny;
-    }
-    const int si = i == 0 ? b.nx : (i == b.nx + 1 ? 1 : i);
-    const int sj = j == 0 ? b.ny : (j == b.ny + 1 ? 1 : j);
-    const int64_t dst = k + (int64_t)j * b.sy + (int64_t)i * b.sx;
-    const int64_t src = k + (int64_t)sj * b.sy + (int64_t)si * b.sx;
     using U = storage_bits<ST>;
     global_ptr<U> f[3] = {as_global((U*)a.u), as_global((U*)a.v), as_global((U*)a.w)};
+    const int64_t n = (int64_t)nhalo * b.nz;
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < n; g += (int64_t)gridDim.x * 256) {
+        const int k = (int)(g % b.nz);
+        const int h = (int)(g / b.nz);
+        int i, j;
+        if (h < b.nx + 2) {
+            i = h;
+            j = 0;
+        } else if (h < 2 * (b.nx + 2)) {
+            i = h - (b.nx + 2);
+            j = b.ny + 1;
+        } else if (h < 2 * (b.nx + 2) + b.ny) {
+            i = 0;
+            j = 1 + h - 2 * (b.nx + 2);
+        } else {
+            i = b.nx + 1;
+            j = 1 + h - 2 * (b.nx + 2) - b.ny;
+        }
+        const int si = i == 0 ? b.nx : (i == b.nx + 1 ? 1 : i);
+        const int sj = j == 0 ? b.ny : (j == b.ny + 1 ? 1 : j);
+        const int64_t dst = k + (int64_t)j * b.sy + (int64_t)i * b.sx;
+        const int64_t src = k + (int64_t)sj * b.sy + (int64_t)si * b.sx;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) f[q][dst] = f[q][src];
+        for (int q = 0; q < 3; ++q) f[q][dst] = f[q][src];
+    }
 }
 
 // SplitMix64 finaliser (Steele, Lea and Flood, OOPSLA 2014).
@@ -463,10 +466,17 @@ hipError_t dispatch_batched(int32_t storage, int32_t chunk, int32_t kind, const 
     }
 }
 
-int64_t max_halo_elems(const pw_plan* p) {
-    int64_t m = 0;
-    for (const pw_shape& s : p->shapes) m = std::max<int64_t>(m, (int64_t)(2 * (s.nx + 2) + 2 * s.ny) * s.nz);
-    return m;
+// Workgroups per domain of the halo fill: the mean domain's halo in blocks
+// of 256 elements (larger domains loop), at most the largest domain's.
+int64_t halo_blocks(const pw_plan* p) {
+    int64_t m = 0, sum = 0;
+    for (const pw_shape& s : p->shapes) {
+        const int64_t e = (int64_t)(2 * (s.nx + 2) + 2 * s.ny) * s.nz;
+        m = std::max<int64_t>(m, e);
+        sum += e;
+    }
+    const int64_t mean = sum / std::max<int64_t>(1, (int64_t)p->shapes.size());
+    return std::max<int64_t>(1, std::min((m + 255) / 256, (mean + 255) / 256));
 }
 
 }  // namespace
@@ -654,8 +664,7 @@ int32_t pw_fill_halo_batched(const pw_plan* plan, int32_t ndomains, const pw_dom
     if (!plan || !d_args) return PW_ERR_INVALID_ARG;
     if (ndomains != plan->ndomains) return PW_ERR_PLAN_MISMATCH;
     if (!plan->batch.d_table) return PW_ERR_UNSUPPORTED;
-    const int64_t blocks = (max_halo_elems(plan) + 255) / 256;
-    dim3 grid((unsigned)blocks, (unsigned)ndomains);
+    dim3 grid((unsigned)halo_blocks(plan), (unsigned)ndomains);
     hipStream_t s = static_cast<hipStream_t>(stream);
     const BatchDomain* tb = plan->batch.d_table;
     switch (plan->storage) {
