@@ -153,3 +153,82 @@ def test_f64_column_top_ignores_values_above_the_top(tuning):
         assert top_ok, "%s(nz) must not read the planted values" % name
         den = np.max(np.abs(oi[fin]))
         assert np.max(np.abs(g[fin] - oi[fin])) <= F64_TOL * den
+
+
+def padded_domain(p, storage, pad, sentinel):
+    """u, v, w, su, sv, sw of `p` with packed columns (sy = nz) and a plane
+    stride padded by `pad` elements; every element starts at `sentinel`, the
+    inputs' views then hold the fields.  Returns (buffers, views)."""
+    dt = B.torch_dtype(storage)
+    nx, ny, nz = p.nx, p.ny, p.nz
+    sx = (ny + 2) * nz + pad
+    bufs = [torch.full(((nx + 1) * sx + (ny + 2) * nz,), sentinel, dtype=dt, device=DEV) for _ in range(6)]
+    views = [b.as_strided((nx + 2, ny + 2, nz), (sx, nz, 1)) for b in bufs]
+    for v, a in zip(views[:3], (p.u, p.v, p.w)):
+        v.copy_(B.to_storage(a, storage, 1.0, DEV))
+    return bufs, views
+
+
+def padding_untouched(buf, p, pad, sentinel):
+    """The `pad` elements after each plane's (ny + 2) nz still hold the sentinel."""
+    if pad == 0:
+        return True
+    plane = (p.ny + 2) * p.nz
+    h = buf.float().cpu().numpy()
+    gaps = np.concatenate([h[i * (plane + pad) + plane:(i + 1) * (plane + pad)] for i in range(p.nx + 1)])
+    return bool(np.all(gaps == sentinel))
+
+
+@pytest.mark.parametrize("storage", [B.F64, B.BF16], ids=["f64", "bf16"])
+@pytest.mark.parametrize("pad", [16, 3], ids=["pad16-vector", "pad3-scalar"])
+def test_march_padded_plane_stride_matches_packed(storage, pad):
+    """Packed columns with a padded plane stride run the march kernel (vector
+    loads when the stride keeps 16-byte alignment, element loads otherwise);
+    the interior equals the packed layout's bit for bit, and the padding
+    between planes is never written."""
+    p = inputs.make_problem(9, 70, 64, seed=91)          # 9 chunks of 512 per plane: the compact tile order
+    tuning = {"variant": B.VARIANT_MARCH, "chunk": 512, "seg": 4}
+    ref = device_domain(p, storage)
+    ref.run(B.Plan(storage, [B.shape_of(ref.u)], tuning))
+    bufs, views = padded_domain(p, storage, pad, -5.0)
+    c = p.coeffs
+    tz = [torch.from_numpy(x).to(DEV) for x in c.arrays()]
+    d = B.DeviceDomain(*views[:3], c.tcx, c.tcy, *tz, outputs=views[3:])
+    plan = B.Plan(storage, [B.shape_of(views[0])], tuning)
+    assert plan.info()["variant"] == B.VARIANT_MARCH
+    d.run(plan)
+    torch.cuda.synchronize()
+    for o, r in zip(d.outputs, ref.outputs):
+        assert same_bits(o[1:-1, 1:-1], r[1:-1, 1:-1])
+    for b in bufs[3:]:
+        assert padding_untouched(b, p, pad, -5.0)
+
+
+def test_batched_padded_plane_strides_match_single_calls():
+    """A batch mixing a vector-aligned padded plane stride, an odd one and a
+    packed domain (the plan then takes element loads for all): every domain's
+    interior equals its single-domain call on packed arrays bit for bit, and
+    no padding is written."""
+    specs = [((7, 40, 64), 16), ((9, 33, 96), 3), ((5, 24, 128), 0)]
+    probs, bufs, recs = [], [], []
+    for d, ((nx, ny, nz), pad) in enumerate(specs):
+        p = inputs.make_problem(nx, ny, nz, seed=930 + d)
+        b, v = padded_domain(p, B.F64, pad, -5.0)
+        tz = [torch.from_numpy(x).to(DEV) for x in p.coeffs.arrays()]
+        for o in v[3:]:
+            o.zero_()
+        recs.append(B.domain_record(*v, p.coeffs.tcx, p.coeffs.tcy, *tz))
+        probs.append((p, pad, v, tz))
+        bufs.append(b)
+    plan = B.Plan(B.F64, [r.shape for r in recs], {"chunk": 512, "seg": 16})
+    B.advect_batched(plan, B.domain_args_tensor(recs, DEV))
+    torch.cuda.synchronize()
+    assert plan.error_count() == 0
+    for (p, pad, v, tz), b in zip(probs, bufs):
+        ref = device_domain(p, B.F64)
+        ref.run(B.Plan(B.F64, [B.shape_of(ref.u)], {"variant": B.VARIANT_MARCH, "chunk": 512, "seg": 5}))
+        torch.cuda.synchronize()
+        for o, r in zip(v[3:], ref.outputs):
+            assert same_bits(o[1:-1, 1:-1], r[1:-1, 1:-1])
+        for o in b[3:]:
+            assert padding_untouched(o, p, pad, -5.0)
