@@ -268,3 +268,33 @@ def test_kahan_product_differences_round_correctly_where_naive_fp32_does_not(sto
         assert lib_wrong <= 0.01, "s%s: %.3f of the library's outputs are not correctly rounded" % (name, lib_wrong)
         assert naive_wrong >= 0.05 and naive_wrong >= 5 * lib_wrong, \
             "s%s: the fields do not separate compensated from naive FP32 (%.3f vs %.3f)" % (name, lib_wrong, naive_wrong)
+
+
+@pytest.mark.parametrize("tuning", [None, {"variant": B.VARIANT_DIRECT}], ids=["march", "direct"])
+def test_fp32_storage_keeps_denormal_results(tuning):
+    """Fields scaled by 2^-64 (exactly; still normal FP32 values) put every FP32
+    output below 2^-126, in the denormal range, and the products of the flux
+    terms with them.  With no flush to zero anywhere, the results follow the
+    oracle on the same stored inputs to within a few denormal spacings
+    (2^-149) plus the usual relative error; a flush would return zeros."""
+    p = inputs.make_problem(24, 20, 64, seed=4242)
+    s = 2.0 ** -64
+    fields = [B.to_storage(a * s, B.F32, 1.0, DEV) for a in (p.u, p.v, p.w)]
+    c = p.coeffs
+    tz = [torch.from_numpy(x).to(DEV) for x in c.arrays()]
+    d = B.DeviceDomain(*fields, c.tcx, c.tcy, *tz)
+    d.run(B.Plan(B.F32, [B.shape_of(fields[0])], tuning))
+    torch.cuda.synchronize()
+    deq = [f.double().cpu().numpy() for f in fields]
+    ref = oracle.advect(*deq, c.tcx, c.tcy, *c.arrays())
+    for name, o, r in zip(("su", "sv", "sw"), d.outputs, ref):
+        g = o.double().cpu().numpy()[1:-1, 1:-1]
+        ri = r[1:-1, 1:-1]
+        m = np.max(np.abs(ri))
+        assert 2.0 ** -140 < m < 2.0 ** -126, "%s: outputs must lie in the denormal range (max %.3e)" % (name, m)
+        live = ri != 0
+        assert np.count_nonzero(g[live]) >= 0.99 * np.count_nonzero(live), "%s: denormal results flushed" % name
+        err = np.max(np.abs(g - ri))
+        bound = 8 * 2.0 ** -149 + (UNIT_ROUNDOFF[B.F32] + FP32_ARITH) * m
+        say("f32 denormal", name, tuning, "max %.3e err %.3e bound %.3e" % (m, err, bound))
+        assert err <= bound, "%s: %.3e > %.3e" % (name, err, bound)
