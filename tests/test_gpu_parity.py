@@ -232,3 +232,21 @@ def test_batched_padded_plane_strides_match_single_calls():
             assert same_bits(o[1:-1, 1:-1], r[1:-1, 1:-1])
         for o in b[3:]:
             assert padding_untouched(o, p, pad, -5.0)
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 257), (5, 3, 300), (2, 2, 513)], ids=lambda s: "x".join(map(str, s)))
+def test_tall_columns_take_the_direct_kernel(shape):
+    """Columns taller than the march kernel's LDS window allows (nz > 256):
+    the automatic plan takes the direct kernel, which matches the oracle to
+    1e-12; an explicit march plan and a batched plan are refused."""
+    nx, ny, nz = shape
+    p = inputs.make_problem(nx, ny, nz, seed=2000 + nz)
+    ref = oracle.advect_problem(p)
+    d, plan = _run(p, {})
+    assert plan.info()["variant"] == B.VARIANT_DIRECT
+    compare_f64(d, ref, where="%s" % (shape,))
+    check_halo_untouched(d)
+    with pytest.raises(RuntimeError):
+        B.Plan(B.F64, [B.shape_of(d.u)], {"variant": B.VARIANT_MARCH})
+    bplan = B.Plan(B.F64, [B.shape_of(d.u)] * 2, None)
+    assert bplan.info()["batched_workgroups"] == 0
