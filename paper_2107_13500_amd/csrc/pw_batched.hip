@@ -104,7 +104,7 @@ __device__ __forceinline__ int find_domain(const BatchDomain* table, int ndom, i
 __device__ __forceinline__ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
 // Which per-tile code paths a batched kernel carries.  Every path inlined
-// into the persistent kernel counts towards its register allocation, so a
+// into the batched kernel counts towards its register allocation, so a
 // plan launches the narrowest kind its shapes allow:
 //   kFixedNz  vector loads, column heights 64 / 96 / 128 only;
 //   kVector   vector loads, any column height;
