@@ -161,8 +161,10 @@ typedef struct pw_plan_info {
     int64_t tiles;        /* (chunk, segment) tiles over all domains */
     int64_t lds_bytes;    /* dynamic LDS per workgroup */
     int64_t points;       /* interior grid points over all domains */
-    int64_t batched_workgroups;  /* grid of pw_advect_batched: persistent, or one per tile padded to
-                                    whole blocks of 64 tiles (0 if unavailable) */
+    int64_t batched_workgroups;  /* grid of pw_advect_batched: persistent, or one per tile (padded to
+                                    whole blocks of 64 tiles; for BF16 and FP16 plans, 8 times the
+                                    longest per-XCD queue of the plan's dispatch order); 0 if
+                                    unavailable */
 } pw_plan_info;
 
 /* Create a plan for `ndomains` domains (1 for pw_advect; the batch size for

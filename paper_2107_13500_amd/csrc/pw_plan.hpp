@@ -42,6 +42,7 @@ struct BatchState {
     Launch launch;               // shared kernel shape (chunk, seg, wpad for the largest nz)
     BatchDomain* d_table = nullptr;
     unsigned long long* d_errors = nullptr;
+    const int32_t* d_order = nullptr;   // one workgroup per tile: each workgroup's tile (-1: none), or NULL
     int device = -1;
     bool vec_shapes = false;     // every shape allows 16-byte loads
     int32_t kind = 2;            // code paths of the batched kernel (BatchKind in pw_batched.hip)
